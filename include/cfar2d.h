@@ -1,0 +1,252 @@
+/*
+ * cfar2d.h -- C ABI of libcfar2d.so: integral-image 2D cell-averaging CFAR
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the detector of Rohman, Andra and Nishimoto, "Optimized 2D
+ * CA-CFAR for Drone-Mounted Radar Signal Processing Using Integral Image
+ * Algorithm" (arXiv 2012.11077), Sec. II.B:
+ *
+ *   map X in R^{M x N} (Sec. II.A): here `rows` range bins x `cols`
+ *       slow-time-frequency bins, row-major, frequency contiguous, with a
+ *       leading dimension `ld` >= cols (in elements);
+ *   integral image (eq. 3): S(i,j) = sum of X over rows <= i, cols <= j;
+ *   rectangle sum (eq. 4): four corners of S;
+ *   training cells: the rectangle of half-widths (guard + train) around the
+ *       cell under test (CUT) minus the guard rectangle of half-widths guard
+ *       (Table I names these "Guard Cell" and "Background Cell"), both
+ *       clipped to the map; N = number of training cells inside the map;
+ *   threshold (eq. 2): T = alpha * A, A = (training sum) / N, with
+ *       alpha = N (Pfa^(-1/N) - 1) (the exponent printed in eq. 2 has the
+ *       opposite sign, which gives a negative alpha);
+ *   decision (eq. 1): target (mask = 1) iff CUT > T; N = 0 gives mask = 0.
+ *
+ * Conventions for every entry point:
+ *   - All map, mask, SAT and workspace pointers are DEVICE pointers owned by
+ *     the caller, unless an argument says otherwise.  The library allocates
+ *     and frees none of them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls enqueue work and return; the caller synchronises the stream
+ *     before it reads the outputs.
+ *   - Every argument is validated on the host before any device work; on
+ *     error nothing is enqueued and nothing is written.  The return value is
+ *     a cfar_status; cfar_last_error() describes the last failure of the
+ *     calling thread.
+ *   - Preconditions that are not checked on the device: X is finite and
+ *     >= 0 (a square-law power map, which is what alpha assumes), and
+ *     |X| <= 1e30.
+ *   - Device faults surface as CFAR_EDEVICE from the next call that checks
+ *     the HIP runtime.
+ */
+#ifndef CFAR2D_H
+#define CFAR2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+typedef enum {
+    CFAR_OK = 0,
+    CFAR_EINVAL = -1,    /* an argument is invalid (nothing enqueued)          */
+    CFAR_ENOSPC = -2,    /* sat_bytes or ws_bytes is too small                  */
+    CFAR_EDEVICE = -3,   /* the HIP runtime reported an error                   */
+    CFAR_EAGAIN = -4,    /* server queue full: submit again later               */
+    CFAR_ESHUTDOWN = -5  /* server is shutting down / frame was never started   */
+} cfar_status;
+
+/* Storage type of the map. */
+typedef enum { CFAR_F32 = 0, CFAR_F64 = 1 } cfar_dtype;
+
+/* Precision forms.
+ *   PLAIN: the integral image of eq. (3) is materialised in FP64 in device
+ *          memory (by sat2d), then the eight-corner stencil of eq. (4) reads it.
+ *   TILED: the integral image is never materialised.  Each work tile builds
+ *          tile-local prefix sums of its own rows and columns (plus the window
+ *          halo) with FP64 carries and evaluates the eight corners from them;
+ *          the map stays in its storage type (FP32 or FP64).  One pass over X. */
+typedef enum { CFAR_FORM_PLAIN = 0, CFAR_FORM_TILED = 1 } cfar_form;
+
+/* CFAR window (Table I, eq. 2): half-widths per axis, in cells.  The outer
+ * half-widths are guard + train.  train_r + train_f must be > 0; 0 < pfa < 1. */
+typedef struct {
+    int32_t guard_r, guard_f;  /* guard half-widths along rows (range) / cols (frequency) */
+    int32_t train_r, train_f;  /* training half-widths beyond the guard                   */
+    double pfa;                /* design probability of false alarm                       */
+} cfar_window;
+
+/* One map and its outputs. */
+typedef struct {
+    const void *x;        /* device: rows x cols map, leading dimension ld (elements)      */
+    int32_t dtype;        /* cfar_dtype                                                     */
+    int32_t reserved0;    /* must be 0                                                      */
+    int64_t rows, cols, ld;
+    cfar_window win;
+    uint8_t *mask;        /* device: rows x cols, leading dimension ld_mask, 0/1 per cell   */
+    int64_t ld_mask;      /* >= cols; also the leading dimension of the optional outputs    */
+    double *train_sum;    /* device, optional (NULL = skip): training sum per cell          */
+    double *threshold;    /* device, optional (NULL = skip): T per cell (+inf when N = 0)   */
+} cfar_map;
+
+/* ------------------------------------------------------------------------ */
+/* Integral image (eq. 3)                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of the SAT output of sat2d for a rows x cols map.
+ *   PLAIN: rows*cols FP64, row-major, leading dimension cols; entry (i,j) is
+ *          S(i,j) of eq. (3) (the zero boundary S(-1,.) = S(.,-1) = 0 is implied).
+ *   TILED: three regions, each starting at a 256-byte boundary:
+ *          (a) FP32 tile-local sums, rows x cols row-major: entry (i,j) is the
+ *              sum of X over rows 32*floor(i/32)..i and cols 32*floor(j/32)..j;
+ *          (b) FP64 row lines, ceil(rows/32) x cols: line I, entry j is
+ *              S(32*I - 1, j) (0 for I = 0);
+ *          (c) FP64 column lines, ceil(cols/32) x rows: line J, entry i is
+ *              S(i, 32*J - 1) (0 for J = 0).
+ *          Then S(i,j) = rowline[I][j] + colline[J][i] - rowline[I][32*J-1]
+ *          + local(i,j), with I = i/32, J = j/32 and the corner term 0 when J = 0.
+ * Returns 0 when rows or cols < 1. */
+size_t sat2d_bytes(int64_t rows, int64_t cols, int32_t form);
+
+/* Bytes of device workspace sat2d needs (tile aggregates and carries). */
+size_t sat2d_workspace_bytes(int64_t rows, int64_t cols, int32_t form);
+
+/* Integral image of X (eq. 3) in the layout of `form` (see sat2d_bytes).
+ * x: device map (dtype, rows, cols, ld).  sat_out: device, >= sat2d_bytes.
+ * ws: device scratch, >= sat2d_workspace_bytes; its contents on entry do not
+ * matter.  FP32 input is promoted to FP64 exactly before it is summed.
+ * Errors: CFAR_EINVAL (rows/cols < 1, ld < cols, NULL pointer, unknown dtype
+ * or form), CFAR_ENOSPC (sat_bytes or ws_bytes too small), CFAR_EDEVICE. */
+int sat2d(const void *x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int32_t form,
+          void *sat_out, size_t sat_bytes, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* CA-CFAR (eqs. 1, 2, 4)                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Device workspace bytes for cfar2d / cfar2d_batched over `n` maps in `form`
+ * (PLAIN: the FP64 SAT of the largest map plus its aggregates, plus the
+ * threshold tables; TILED: descriptors, work counters and threshold tables).
+ * Returns 0 when an argument is invalid (cfar_last_error() says which). */
+size_t cfar_workspace_bytes(const cfar_map *maps, int32_t n, int32_t form);
+
+/* CA-CFAR over one map.  m: host pointer to the descriptor (its x, mask and
+ * optional outputs are device pointers).  ws: device, >= cfar_workspace_bytes
+ * for this map; contents on entry do not matter; it must not be used by
+ * another call until this call's work on `stream` has finished.
+ * Errors: CFAR_EINVAL (see the conventions above: rows/cols < 1, ld or
+ * ld_mask < cols, negative half-width, train_r + train_f == 0, pfa not in
+ * (0,1), NULL x/mask, unknown dtype/form, reserved0 != 0), CFAR_ENOSPC,
+ * CFAR_EDEVICE. */
+int cfar2d(const cfar_map *m, int32_t form, void *ws, size_t ws_bytes, void *stream);
+
+/* Batch flags. */
+enum {
+    CFAR_BATCH_GRAPH = 1  /* capture the launch sequence in a hipGraph and replay it when
+                             the same batch layout (n, ws, per-map work) comes again */
+};
+
+/* CA-CFAR over `n` maps of any sizes, each with its own window and Pfa.
+ * maps: host array of n descriptors.  TILED: one persistent launch over the
+ * work tiles of all maps (plus one small kernel that builds the threshold
+ * tables); each map's tile shape depends only on that map's own size, window
+ * and dtype, so every map's result is the same alone and in any batch.
+ * PLAIN: the per-map FP64 form, one sat2d + stencil per map on `stream`.
+ * Errors as cfar2d; map k's problems are reported with its index. */
+int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tile plans (TILED form) and the autotuned plan table                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t k_cols;        /* columns per lane: 2, 4 or 8 (a 64-lane wave covers 64*k_cols cols) */
+    int32_t rows_per_unit; /* output rows per work unit, 8..4096                                  */
+} cfar_plan;
+
+/* The plan the TILED form uses for map m (from the loaded table, else the
+ * built-in cost model).  Depends only on m's dtype, rows, cols and window. */
+int cfar_plan_for(const cfar_map *m, cfar_plan *out);
+
+/* Load a plan table written by the autotuner (text; one rule per line, see
+ * paper_2012_11077_amd/autotune.py).  NULL or "" restores the built-in model.
+ * Not thread-safe with concurrent TILED calls. */
+int cfar_plan_load(const char *path);
+
+/* TILED CA-CFAR over one map with an explicit plan (the autotuner's probe). */
+int cfar2d_with_plan(const cfar_map *m, const cfar_plan *plan, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Streaming server: continuous batching of frames from many streams         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct cfar_server cfar_server;
+
+typedef struct {
+    size_t device_budget_bytes; /* device memory the server may hold for frames in flight     */
+    int32_t max_inflight_frames;/* frames admitted to the device at once                       */
+    int32_t n_hip_streams;      /* HIP streams batches rotate over (1..16)                     */
+    int32_t queue_depth;        /* submitted-but-not-admitted frames; more gives CFAR_EAGAIN   */
+    int32_t max_batch_frames;   /* frames per launched batch (<= max_inflight_frames)          */
+} cfar_server_opts;
+
+typedef struct {
+    uint64_t ticket, user_tag;
+    int32_t status;             /* CFAR_OK, CFAR_EDEVICE or CFAR_ESHUTDOWN                     */
+    int32_t reserved;
+    int64_t t_submit_ns, t_start_ns, t_done_ns; /* CLOCK_MONOTONIC                             */
+} cfar_completion;
+
+typedef struct {
+    uint64_t submitted, completed, failed, batches;
+    size_t device_bytes_in_use, device_bytes_peak;
+    int32_t inflight_frames, queued_frames;
+} cfar_server_stats;
+
+/* Create a server: allocates its device pool (device_budget_bytes, clamped
+ * to the free device memory) and starts its scheduler thread. */
+int cfar_server_create(const cfar_server_opts *opts, cfar_server **out);
+
+/* Submit one frame (TILED form, FP32 or FP64).  x_on_host = 1: frame->x and
+ * frame->mask are HOST pointers (pinned memory gives overlap); the server
+ * copies X in and the mask out, and train_sum/threshold must be NULL.
+ * x_on_host = 0: all pointers are device pointers.  Buffers must stay valid
+ * until the ticket completes.  Never blocks: CFAR_EAGAIN when the queue is
+ * full, CFAR_EINVAL for a bad frame or one larger than the device budget,
+ * CFAR_ESHUTDOWN after destroy began. */
+int cfar_submit(cfar_server *s, const cfar_map *frame, int32_t x_on_host, uint64_t user_tag,
+                uint64_t *ticket_out);
+
+/* Collect up to `max` completions, waiting up to timeout_us (0 = do not
+ * wait, < 0 = wait for at least one).  *n_out = number written.  A timeout
+ * with nothing completed returns CFAR_OK with *n_out = 0. */
+int cfar_poll(cfar_server *s, cfar_completion *out, int32_t max, int32_t timeout_us, int32_t *n_out);
+
+/* Counters of the server (thread-safe snapshot). */
+int cfar_server_stats_get(cfar_server *s, cfar_server_stats *out);
+
+/* Stop accepting frames (later submits give CFAR_ESHUTDOWN) and wait until
+ * nothing is in flight.  drain_queued = 1: frames still queued are run;
+ * 0: they complete with status CFAR_ESHUTDOWN without touching the device.
+ * Completions stay pollable afterwards.  Idempotent. */
+int cfar_server_shutdown(cfar_server *s, int32_t drain_queued);
+
+/* cfar_server_shutdown(s, 0) if not yet done, then stop the scheduler thread
+ * and free the server, its streams and its device pool.  Completions not yet
+ * polled are dropped. */
+int cfar_server_destroy(cfar_server *s);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *cfar_last_error(void);
+
+/* Library version string. */
+const char *cfar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFAR2D_H */

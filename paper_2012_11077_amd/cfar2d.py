@@ -1,0 +1,316 @@
+"""ctypes binding of libcfar2d.so (C ABI in include/cfar2d.h).
+
+Argument marshalling only: every step of the detector runs in the library's
+HIP kernels.  PyTorch provides device memory and streams; tensors are passed
+by their data pointers.  If the library is not built, every call raises.
+
+Functions follow the C names: :func:`sat2d`, :func:`cfar2d`,
+:func:`cfar2d_batched`, :func:`workspace_bytes`, :func:`plan_for`,
+:func:`plan_load`, :func:`cfar2d_with_plan`, and the streaming server
+:class:`Server` (``cfar_server_create`` / ``cfar_submit`` / ``cfar_poll`` /
+``cfar_server_shutdown`` / ``cfar_server_destroy``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcfar2d.so")
+
+CFAR_OK, CFAR_EINVAL, CFAR_ENOSPC, CFAR_EDEVICE, CFAR_EAGAIN, CFAR_ESHUTDOWN = 0, -1, -2, -3, -4, -5
+F32, F64 = 0, 1
+PLAIN, TILED = 0, 1
+BATCH_GRAPH = 1
+STATUS_NAMES = {0: "CFAR_OK", -1: "CFAR_EINVAL", -2: "CFAR_ENOSPC", -3: "CFAR_EDEVICE",
+                -4: "CFAR_EAGAIN", -5: "CFAR_ESHUTDOWN"}
+
+
+class CfarError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class Window(ctypes.Structure):
+    _fields_ = [("guard_r", ctypes.c_int32), ("guard_f", ctypes.c_int32),
+                ("train_r", ctypes.c_int32), ("train_f", ctypes.c_int32), ("pfa", ctypes.c_double)]
+
+
+class Map(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("win", Window), ("mask", ctypes.c_void_p), ("ld_mask", ctypes.c_int64),
+                ("train_sum", ctypes.c_void_p), ("threshold", ctypes.c_void_p)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("k_cols", ctypes.c_int32), ("rows_per_unit", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device_budget_bytes", ctypes.c_size_t), ("max_inflight_frames", ctypes.c_int32),
+                ("n_hip_streams", ctypes.c_int32), ("queue_depth", ctypes.c_int32),
+                ("max_batch_frames", ctypes.c_int32)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("user_tag", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("t_submit_ns", ctypes.c_int64),
+                ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("device_bytes_in_use", ctypes.c_size_t), ("device_bytes_peak", ctypes.c_size_t),
+                ("inflight_frames", ctypes.c_int32), ("queued_frames", ctypes.c_int32)]
+
+
+_lib = None
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_PMap = ctypes.POINTER(Map)
+
+
+def lib():
+    """Load libcfar2d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcfar2d.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.cfar_last_error.restype = ctypes.c_char_p
+        L.cfar_version.restype = ctypes.c_char_p
+        L.sat2d_bytes.argtypes = [_i64, _i64, _i32]
+        L.sat2d_bytes.restype = _sz
+        L.sat2d_workspace_bytes.argtypes = [_i64, _i64, _i32]
+        L.sat2d_workspace_bytes.restype = _sz
+        L.sat2d.argtypes = [_vp, _i32, _i64, _i64, _i64, _i32, _vp, _sz, _vp, _sz, _vp]
+        L.cfar_workspace_bytes.argtypes = [_PMap, _i32, _i32]
+        L.cfar_workspace_bytes.restype = _sz
+        L.cfar2d.argtypes = [_PMap, _i32, _vp, _sz, _vp]
+        L.cfar2d_batched.argtypes = [_PMap, _i32, _i32, _i32, _vp, _sz, _vp]
+        L.cfar_plan_for.argtypes = [_PMap, ctypes.POINTER(Plan)]
+        L.cfar_plan_load.argtypes = [ctypes.c_char_p]
+        L.cfar2d_with_plan.argtypes = [_PMap, ctypes.POINTER(Plan), _vp, _sz, _vp]
+        if hasattr(L, "cfar_server_create"):
+            L.cfar_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
+            L.cfar_submit.argtypes = [_vp, _PMap, _i32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+            L.cfar_poll.argtypes = [_vp, ctypes.POINTER(Completion), _i32, _i32, ctypes.POINTER(_i32)]
+            L.cfar_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+            L.cfar_server_shutdown.argtypes = [_vp, _i32]
+            L.cfar_server_destroy.argtypes = [_vp]
+        for name in ("sat2d", "cfar2d", "cfar2d_batched", "cfar_plan_for", "cfar_plan_load",
+                     "cfar2d_with_plan"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().cfar_last_error().decode()
+
+
+def version() -> str:
+    return lib().cfar_version().decode()
+
+
+def _check(rc: int) -> None:
+    if rc != CFAR_OK:
+        raise CfarError(rc, last_error())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("map must be float32 or float64, got %s" % t.dtype)
+
+
+def _check_2d(t: torch.Tensor, name: str) -> None:
+    if t.dim() != 2:
+        raise ValueError("%s must be 2D" % name)
+    if t.size(1) > 1 and t.stride(1) != 1:
+        raise ValueError("%s must have unit stride along columns" % name)
+
+
+def make_window(guard_r: int, guard_f: int, train_r: int, train_f: int, pfa: float) -> Window:
+    return Window(int(guard_r), int(guard_f), int(train_r), int(train_f), float(pfa))
+
+
+def make_map(x: torch.Tensor, window, mask: torch.Tensor, train_sum: Optional[torch.Tensor] = None,
+             threshold: Optional[torch.Tensor] = None) -> Map:
+    """C descriptor of one map.  ``window`` is a :class:`Window` or a tuple
+    (guard_r, guard_f, train_r, train_f, pfa).  The mask (uint8) and the
+    optional float64 outputs share the mask's leading dimension."""
+    _check_2d(x, "x")
+    _check_2d(mask, "mask")
+    if mask.dtype != torch.uint8:
+        raise TypeError("mask must be uint8")
+    if tuple(mask.shape) != tuple(x.shape):
+        raise ValueError("mask shape differs from the map")
+    w = window if isinstance(window, Window) else make_window(*window)
+    ldm = mask.stride(0) if mask.size(0) > 1 else mask.size(1)
+    for name, t in (("train_sum", train_sum), ("threshold", threshold)):
+        if t is not None:
+            _check_2d(t, name)
+            if t.dtype != torch.float64 or tuple(t.shape) != tuple(x.shape):
+                raise ValueError("%s must be float64 with the map's shape" % name)
+            if (t.stride(0) if t.size(0) > 1 else t.size(1)) != ldm:
+                raise ValueError("%s must share the mask's leading dimension" % name)
+    ld = x.stride(0) if x.size(0) > 1 else x.size(1)
+    return Map(x.data_ptr(), _dtype_code(x), 0, x.size(0), x.size(1), ld, w, mask.data_ptr(), ldm,
+               train_sum.data_ptr() if train_sum is not None else None,
+               threshold.data_ptr() if threshold is not None else None)
+
+
+def _alloc_ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def sat2d(x: torch.Tensor, form: int = PLAIN, out: Optional[torch.Tensor] = None,
+          ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Integral image (eq. 3) of ``x``.  PLAIN: returns an R x F float64
+    tensor.  TILED: returns the raw byte buffer of the tiled layout (see
+    include/cfar2d.h; :func:`decode_tiled_sat` rebuilds S from it)."""
+    _check_2d(x, "x")
+    L = lib()
+    R, F = x.shape
+    nbytes = L.sat2d_bytes(R, F, form)
+    if nbytes == 0:
+        raise CfarError(CFAR_EINVAL, "invalid shape or form")
+    if out is None:
+        out = (torch.empty((R, F), dtype=torch.float64, device=x.device) if form == PLAIN
+               else torch.empty(nbytes, dtype=torch.uint8, device=x.device))
+    if ws is None:
+        ws = _alloc_ws(L.sat2d_workspace_bytes(R, F, form), x.device)
+    ld = x.stride(0) if R > 1 else F
+    _check(L.sat2d(x.data_ptr(), _dtype_code(x), R, F, ld, form, out.data_ptr(),
+                   out.numel() * out.element_size(), ws.data_ptr(), ws.numel(),
+                   _stream_handle(stream)))
+    return out
+
+
+def decode_tiled_sat(buf: torch.Tensor, rows: int, cols: int) -> torch.Tensor:
+    """S(i,j) from the TILED sat2d layout, as float64 (done on the tensor's
+    device with torch ops: a readback helper, not part of the hot path)."""
+    line = 32
+
+    def up(v):
+        return (v + 255) // 256 * 256
+
+    nI, nJ = (rows + line - 1) // line, (cols + line - 1) // line
+    loc_b = up(rows * cols * 4)
+    row_b = up(nI * cols * 8)
+    raw = buf.view(torch.uint8)
+    loc = raw[:rows * cols * 4].view(torch.float32).view(rows, cols).double()
+    rowline = raw[loc_b:loc_b + nI * cols * 8].view(torch.float64).view(nI, cols)
+    colline = raw[loc_b + row_b:loc_b + row_b + nJ * rows * 8].view(torch.float64).view(nJ, rows)
+    I = torch.arange(rows, device=buf.device) // line
+    J = torch.arange(cols, device=buf.device) // line
+    top = rowline[I][:, :]                      # rows x cols: S(32I-1, j)
+    left = colline[J][:, :].t()                 # rows x cols: S(i, 32J-1)
+    cj = (J * line - 1).clamp(min=0)
+    corner = rowline[I][:, cj] * (J > 0).double()[None, :]
+    return top + left - corner + loc
+
+
+def workspace_bytes(maps: Sequence[Map], form: int) -> int:
+    arr = (Map * len(maps))(*maps)
+    n = lib().cfar_workspace_bytes(arr, len(maps), form)
+    if n == 0:
+        raise CfarError(CFAR_EINVAL, last_error())
+    return int(n)
+
+
+def cfar2d(x: torch.Tensor, window, form: int = TILED, mask: Optional[torch.Tensor] = None,
+           train_sum: Optional[torch.Tensor] = None, threshold: Optional[torch.Tensor] = None,
+           ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """CA-CFAR over one map (eqs. 1-4); returns the uint8 mask."""
+    if mask is None:
+        mask = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    m = make_map(x, window, mask, train_sum, threshold)
+    if ws is None:
+        ws = _alloc_ws(workspace_bytes([m], form), x.device)
+    _check(lib().cfar2d(ctypes.byref(m), form, ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+    return mask
+
+
+def cfar2d_with_plan(x: torch.Tensor, window, k_cols: int, rows_per_unit: int,
+                     mask: Optional[torch.Tensor] = None, train_sum=None, threshold=None,
+                     ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """TILED CA-CFAR with an explicit tile plan (autotuner probe)."""
+    if mask is None:
+        mask = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    m = make_map(x, window, mask, train_sum, threshold)
+    if ws is None:
+        ws = _alloc_ws(workspace_bytes([m], TILED), x.device)
+    p = Plan(int(k_cols), int(rows_per_unit))
+    _check(lib().cfar2d_with_plan(ctypes.byref(m), ctypes.byref(p), ws.data_ptr(), ws.numel(),
+                                  _stream_handle(stream)))
+    return mask
+
+
+class Batch:
+    """A prepared batch: the C descriptor array plus a workspace, reusable
+    across calls on the same tensors (what a serving loop or benchmark does)."""
+
+    def __init__(self, xs: Sequence[torch.Tensor], windows: Sequence, form: int = TILED,
+                 masks: Optional[Sequence[torch.Tensor]] = None, train_sums=None, thresholds=None,
+                 ws: Optional[torch.Tensor] = None):
+        n = len(xs)
+        if n == 0:
+            raise ValueError("empty batch")
+        if masks is None:
+            masks = [torch.empty(x.shape, dtype=torch.uint8, device=x.device) for x in xs]
+        self.xs, self.masks, self.form = list(xs), list(masks), form
+        ts = train_sums or [None] * n
+        th = thresholds or [None] * n
+        self.maps = (Map * n)(*[make_map(xs[i], windows[i], masks[i], ts[i], th[i]) for i in range(n)])
+        need = lib().cfar_workspace_bytes(self.maps, n, form)
+        if need == 0:
+            raise CfarError(CFAR_EINVAL, last_error())
+        self.ws = ws if ws is not None else _alloc_ws(need, xs[0].device)
+        if self.ws.numel() < need:
+            raise CfarError(CFAR_ENOSPC, "workspace too small")
+
+    def run(self, flags: int = BATCH_GRAPH, stream=None) -> List[torch.Tensor]:
+        _check(lib().cfar2d_batched(self.maps, len(self.xs), self.form, flags, self.ws.data_ptr(),
+                                    self.ws.numel(), _stream_handle(stream)))
+        return self.masks
+
+
+def cfar2d_batched(xs: Sequence[torch.Tensor], windows: Sequence, form: int = TILED,
+                   masks=None, train_sums=None, thresholds=None, flags: int = BATCH_GRAPH,
+                   ws: Optional[torch.Tensor] = None, stream=None) -> List[torch.Tensor]:
+    """CA-CFAR over many maps (own sizes, windows and Pfa) in one call."""
+    b = Batch(xs, windows, form, masks, train_sums, thresholds, ws)
+    return b.run(flags, stream)
+
+
+def plan_for(x: torch.Tensor, window) -> Tuple[int, int]:
+    """(k_cols, rows_per_unit) the TILED form uses for this map."""
+    m = make_map(x, window, _mask_like(x))
+    p = Plan()
+    _check(lib().cfar_plan_for(ctypes.byref(m), ctypes.byref(p)))
+    return int(p.k_cols), int(p.rows_per_unit)
+
+
+def _mask_like(x: torch.Tensor) -> torch.Tensor:
+    return torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+
+
+def plan_load(path: Optional[str]) -> None:
+    _check(lib().cfar_plan_load(path.encode() if path else None))

@@ -1,0 +1,642 @@
+// Host side of libcfar2d.so: argument validation, tile plans, workspace
+// layout, launch sequences, hipGraph capture/replay for batches.
+//
+// Method: arXiv 2012.11077, Sec. II.B (eqs. 1-4); see include/cfar2d.h.
+#include "cfar2d.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace cfar {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+int set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_error(hipError_t e, const char *what)
+{
+    return set_error(CFAR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+constexpr int64_t kMaxDim = int64_t(1) << 30;  // rows, cols
+constexpr int32_t kMaxHalf = 1024;             // any half-width
+constexpr int32_t kMaxTiledHf = 250;           // TILED: 64*8 columns per wave minus two halos
+
+int validate_map(const cfar_map *m, int idx, int form)
+{
+    if (!m) return set_error(CFAR_EINVAL, "map %d: NULL descriptor", idx);
+    if (m->reserved0 != 0) return set_error(CFAR_EINVAL, "map %d: reserved0 must be 0", idx);
+    if (m->dtype != CFAR_F32 && m->dtype != CFAR_F64)
+        return set_error(CFAR_EINVAL, "map %d: unknown dtype %d", idx, m->dtype);
+    if (m->rows < 1 || m->cols < 1)
+        return set_error(CFAR_EINVAL, "map %d: rows and cols must be >= 1 (got %lld x %lld)", idx,
+                         (long long)m->rows, (long long)m->cols);
+    if (m->rows > kMaxDim || m->cols > kMaxDim)
+        return set_error(CFAR_EINVAL, "map %d: rows and cols must be <= 2^30", idx);
+    if (m->ld < m->cols) return set_error(CFAR_EINVAL, "map %d: ld < cols", idx);
+    if (m->ld_mask < m->cols) return set_error(CFAR_EINVAL, "map %d: ld_mask < cols", idx);
+    if (!m->x) return set_error(CFAR_EINVAL, "map %d: x is NULL", idx);
+    if (!m->mask) return set_error(CFAR_EINVAL, "map %d: mask is NULL", idx);
+    const cfar_window &w = m->win;
+    if (w.guard_r < 0 || w.guard_f < 0 || w.train_r < 0 || w.train_f < 0)
+        return set_error(CFAR_EINVAL, "map %d: negative guard or training half-width", idx);
+    if (w.train_r + w.train_f == 0) return set_error(CFAR_EINVAL, "map %d: no training cells (train_r + train_f == 0)", idx);
+    if ((int64_t)w.guard_r + w.train_r > kMaxHalf || (int64_t)w.guard_f + w.train_f > kMaxHalf)
+        return set_error(CFAR_EINVAL, "map %d: guard + train half-width above %d", idx, kMaxHalf);
+    if (!(w.pfa > 0.0 && w.pfa < 1.0) || !std::isfinite(w.pfa))
+        return set_error(CFAR_EINVAL, "map %d: pfa must lie in (0, 1)", idx);
+    if (form != CFAR_FORM_PLAIN && form != CFAR_FORM_TILED) return set_error(CFAR_EINVAL, "unknown form %d", form);
+    if (form == CFAR_FORM_TILED && w.guard_f + w.train_f > kMaxTiledHf)
+        return set_error(CFAR_EINVAL, "map %d: TILED form supports guard_f + train_f <= %d (use PLAIN)", idx,
+                         kMaxTiledHf);
+    return CFAR_OK;
+}
+
+static int64_t n_full_of(const cfar_window &w)
+{
+    const int64_t hr = w.guard_r + w.train_r, hf = w.guard_f + w.train_f;
+    return (2 * hr + 1) * (2 * hf + 1) - (int64_t)(2 * w.guard_r + 1) * (2 * w.guard_f + 1);
+}
+
+static size_t lut_bytes(const cfar_map *m) { return align_up((size_t)(n_full_of(m->win) + 1) * 8, 256); }
+
+// ---------------------------------------------------------------------------
+// Tile plans of the TILED form
+// ---------------------------------------------------------------------------
+struct Plan {
+    int k, rs, H, tw, n_strips, n_rchunks;
+};
+
+static bool plan_geometry(const cfar_map *m, int k, int rs, Plan *p)
+{
+    const int hf = m->win.guard_f + m->win.train_f;
+    const int H = (hf + 3) / 4 * 4;
+    const int tw = 64 * k - 2 * H;
+    if (tw < 4 || rs < 1) return false;
+    p->k = k;
+    p->rs = rs;
+    p->H = H;
+    p->tw = tw;
+    p->n_strips = (int)((m->cols + tw - 1) / tw);
+    p->n_rchunks = (int)((m->rows + rs - 1) / rs);
+    return true;
+}
+
+struct PlanRule {
+    int dtype;                    // -1 = any
+    int64_t c_lo, c_hi, r_lo, r_hi;
+    int hf_lo, hf_hi, hr_lo, hr_hi;
+    int k, rs;
+};
+static std::mutex g_plan_mu;
+static std::vector<PlanRule> g_rules;
+
+// Built-in cost model: VALU work per processed column-row for each k (scan
+// cost amortised over k columns), times the columns the strips cover.
+static cfar_plan default_plan(const cfar_map *m)
+{
+    const int hr = m->win.guard_r + m->win.train_r;
+    static const int ks[3] = {2, 4, 8};
+    static const double col_cost[3] = {42.0, 32.0, 27.0};
+    double best = 1e300;
+    int bk = 8;
+    for (int t = 0; t < 3; ++t) {
+        Plan p;
+        if (!plan_geometry(m, ks[t], 64, &p)) continue;
+        const double cost = (double)p.n_strips * 64.0 * ks[t] * col_cost[t];
+        if (cost < best * 0.999) { best = cost; bk = ks[t]; }
+    }
+    int rs = std::max(64, ((4 * hr + 15) / 16) * 16);
+    rs = std::min(rs, 512);
+    if (rs > m->rows) rs = (int)m->rows;
+    cfar_plan out;
+    out.k_cols = bk;
+    out.rows_per_unit = rs;
+    return out;
+}
+
+static cfar_plan choose_plan(const cfar_map *m)
+{
+    const int hr = m->win.guard_r + m->win.train_r, hf = m->win.guard_f + m->win.train_f;
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        for (const PlanRule &r : g_rules) {
+            if (r.dtype >= 0 && r.dtype != m->dtype) continue;
+            if (m->cols < r.c_lo || m->cols > r.c_hi || m->rows < r.r_lo || m->rows > r.r_hi) continue;
+            if (hf < r.hf_lo || hf > r.hf_hi || hr < r.hr_lo || hr > r.hr_hi) continue;
+            Plan p;
+            if (!plan_geometry(m, r.k, r.rs, &p)) continue;
+            cfar_plan out;
+            out.k_cols = r.k;
+            out.rows_per_unit = (int)std::min<int64_t>(r.rs, m->rows);
+            return out;
+        }
+    }
+    return default_plan(m);
+}
+
+static bool plan_valid(const cfar_map *m, const cfar_plan *p)
+{
+    if (!(p->k_cols == 2 || p->k_cols == 4 || p->k_cols == 8)) return false;
+    if (p->rows_per_unit < 1 || p->rows_per_unit > 4096) return false;
+    Plan g;
+    return plan_geometry(m, p->k_cols, p->rows_per_unit, &g);
+}
+
+// ---------------------------------------------------------------------------
+// Descriptors
+// ---------------------------------------------------------------------------
+static MapDesc make_desc(const cfar_map *m, const Plan *p, double *lut)
+{
+    MapDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.x = m->x;
+    d.mask = m->mask;
+    d.train_sum = m->train_sum;
+    d.thresh = m->threshold;
+    d.lut = lut;
+    d.ld = m->ld;
+    d.ld_mask = m->ld_mask;
+    d.neg_log_pfa = -std::log(m->win.pfa);
+    d.rows = (int32_t)m->rows;
+    d.cols = (int32_t)m->cols;
+    d.gr = m->win.guard_r;
+    d.gf = m->win.guard_f;
+    d.hr = m->win.guard_r + m->win.train_r;
+    d.hf = m->win.guard_f + m->win.train_f;
+    d.dtype = m->dtype;
+    d.n_full = (int32_t)n_full_of(m->win);
+    if (p) {
+        d.k_cols = p->k;
+        d.rs = p->rs;
+        d.halo_f = p->H;
+        d.tw = p->tw;
+        d.n_strips = p->n_strips;
+        d.n_rchunks = p->n_rchunks;
+        const size_t es = m->dtype == CFAR_F32 ? 4 : 8;
+        const bool x_vec = ((uintptr_t)m->x % 16 == 0) && ((m->ld * (int64_t)es) % 16 == 0);
+        const bool m_vec = ((uintptr_t)m->mask % 4 == 0) && (m->ld_mask % 4 == 0);
+        d.vec_ok = (x_vec ? 1 : 0) | (m_vec ? 2 : 0);
+    }
+    return d;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layouts
+// ---------------------------------------------------------------------------
+static size_t plain_single_ws(const cfar_map *m)
+{
+    return align_up((size_t)m->rows * (size_t)m->cols * 8, 256) + sat_ws_bytes(m->rows, m->cols) + lut_bytes(m);
+}
+
+struct TiledLayout {
+    size_t head_bytes;     // header + descriptors + unit tables (copied from the host)
+    size_t off_desc, off_base, off_umap, off_lut;
+    std::vector<size_t> lut_off;  // per map, relative to ws
+    size_t total;
+};
+
+static TiledLayout tiled_layout(const cfar_map *maps, int n, uint64_t total_units)
+{
+    TiledLayout L;
+    L.off_desc = sizeof(BatchHeader);
+    L.off_base = L.off_desc + (size_t)n * sizeof(MapDesc);
+    L.off_umap = align_up(L.off_base + (size_t)n * 4, 16);
+    L.head_bytes = align_up(L.off_umap + (size_t)total_units * 4, 256);
+    L.off_lut = L.head_bytes;
+    size_t off = L.off_lut;
+    L.lut_off.resize(n);
+    for (int i = 0; i < n; ++i) {
+        L.lut_off[i] = off;
+        off += lut_bytes(&maps[i]);
+    }
+    L.total = off;
+    return L;
+}
+
+static uint64_t units_of(const Plan &p) { return (uint64_t)p.n_strips * (uint64_t)p.n_rchunks; }
+
+// ---------------------------------------------------------------------------
+// Batch contexts: pinned staging buffers (double-buffered per stream and
+// workspace) and the hipGraphs captured on them.
+// ---------------------------------------------------------------------------
+struct Slot {
+    void *pinned = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool recorded = false;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    // signature of the captured graph
+    size_t sig_head = 0;
+    uint32_t sig_units = 0, sig_blocks = 0, sig_n = 0;
+};
+struct BatchCtx {
+    Slot slot[2];
+    int next = 0;
+    std::mutex mu;
+};
+static std::mutex g_ctx_mu;
+static std::map<std::pair<void *, void *>, std::unique_ptr<BatchCtx>> g_ctx;
+
+static BatchCtx *get_ctx(hipStream_t s, void *ws)
+{
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    auto &p = g_ctx[std::make_pair((void *)s, ws)];
+    if (!p) p.reset(new BatchCtx());
+    return p.get();
+}
+
+static int slot_reserve(Slot &sl, size_t bytes)
+{
+    if (sl.recorded) {
+        hipError_t e = hipEventSynchronize(sl.done);
+        if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(staging)");
+        sl.recorded = false;
+    }
+    if (!sl.done) {
+        hipError_t e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_error(e, "hipEventCreate");
+    }
+    if (sl.cap < bytes) {
+        if (sl.exec) { (void)hipGraphExecDestroy(sl.exec); sl.exec = nullptr; }
+        if (sl.graph) { (void)hipGraphDestroy(sl.graph); sl.graph = nullptr; }
+        if (sl.pinned) (void)hipHostFree(sl.pinned);
+        sl.pinned = nullptr;
+        size_t cap = std::max<size_t>(bytes, 64 << 10);
+        hipError_t e = hipHostMalloc(&sl.pinned, cap, hipHostMallocDefault);
+        if (e != hipSuccess) { sl.cap = 0; return hip_error(e, "hipHostMalloc(staging)"); }
+        sl.cap = cap;
+    }
+    return CFAR_OK;
+}
+
+// Enqueue: descriptor copy, table kernel, persistent kernel.
+static int enqueue_tiled_batch(const Slot &sl, const TiledLayout &L, char *ws, uint32_t n, uint32_t total_units,
+                               hipStream_t stream)
+{
+    hipError_t e = hipMemcpyAsync(ws, sl.pinned, L.head_bytes, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(descriptors)");
+    MapDesc dummy;
+    std::memset(&dummy, 0, sizeof dummy);
+    const MapDesc *descs = (const MapDesc *)(ws + L.off_desc);
+    BatchHeader *hdr = (BatchHeader *)ws;
+    e = launch_lut(descs, dummy, (int)n, &hdr->counter, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
+    FusedArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.descs = descs;
+    a.unit_base = (const uint32_t *)(ws + L.off_base);
+    a.unit_map = (const uint32_t *)(ws + L.off_umap);
+    a.counter = &hdr->counter;
+    a.total_units = total_units;
+    a.n_maps = n;
+    e = launch_fused(a, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
+    return CFAR_OK;
+}
+
+static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, size_t ws_bytes, hipStream_t stream,
+                           const cfar_plan *forced)
+{
+    std::vector<Plan> plans(n);
+    uint64_t total_units = 0;
+    for (int i = 0; i < n; ++i) {
+        cfar_plan cp = forced ? *forced : choose_plan(&maps[i]);
+        if (!plan_geometry(&maps[i], cp.k_cols, cp.rows_per_unit, &plans[i]))
+            return set_error(CFAR_EINVAL, "map %d: no valid tile plan", i);
+        total_units += units_of(plans[i]);
+    }
+    if (total_units >= (uint64_t)1 << 31) return set_error(CFAR_EINVAL, "batch has too many work units");
+    TiledLayout L = tiled_layout(maps, n, total_units);
+    if (ws_bytes < L.total)
+        return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, L.total);
+    if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
+
+    // Processing order: larger maps first (better tail balance).  A map's
+    // result does not depend on the order.
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return units_of(plans[a]) > units_of(plans[b]); });
+
+    const int resident = fused_resident_blocks();
+    uint32_t blocks = (uint32_t)std::min<uint64_t>((total_units + 3) / 4, (uint64_t)resident);
+    if (blocks == 0) blocks = 1;
+
+    BatchCtx *ctx = get_ctx(stream, ws);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    Slot &sl = ctx->slot[ctx->next];
+    ctx->next ^= 1;
+    int rc = slot_reserve(sl, L.head_bytes);
+    if (rc != CFAR_OK) return rc;
+
+    char *h = (char *)sl.pinned;
+    std::memset(h, 0, sizeof(BatchHeader));
+    BatchHeader *hdr = (BatchHeader *)h;
+    hdr->n_maps = (uint32_t)n;
+    hdr->total_units = (uint32_t)total_units;
+    MapDesc *descs = (MapDesc *)(h + L.off_desc);
+    uint32_t *ubase = (uint32_t *)(h + L.off_base);
+    uint32_t *umap = (uint32_t *)(h + L.off_umap);
+    for (int i = 0; i < n; ++i) descs[i] = make_desc(&maps[i], &plans[i], (double *)((char *)ws + L.lut_off[i]));
+    uint32_t u = 0;
+    for (int oi = 0; oi < n; ++oi) {
+        const int i = order[oi];
+        ubase[i] = u;
+        const uint64_t cnt = units_of(plans[i]);
+        for (uint64_t k = 0; k < cnt; ++k) umap[u++] = (uint32_t)i;
+    }
+
+    const bool use_graph = (flags & CFAR_BATCH_GRAPH) && stream != nullptr;
+    if (use_graph) {
+        const bool match = sl.exec && sl.sig_head == L.head_bytes && sl.sig_units == total_units &&
+                           sl.sig_blocks == blocks && sl.sig_n == (uint32_t)n;
+        if (!match) {
+            if (sl.exec) { (void)hipGraphExecDestroy(sl.exec); sl.exec = nullptr; }
+            if (sl.graph) { (void)hipGraphDestroy(sl.graph); sl.graph = nullptr; }
+            hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
+            rc = enqueue_tiled_batch(sl, L, (char *)ws, (uint32_t)n, (uint32_t)total_units, stream);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(stream, &g);
+            if (rc != CFAR_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+            if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&sl.exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) { (void)hipGraphDestroy(g); sl.exec = nullptr; return hip_error(e, "hipGraphInstantiate"); }
+            sl.graph = g;
+            sl.sig_head = L.head_bytes;
+            sl.sig_units = (uint32_t)total_units;
+            sl.sig_blocks = blocks;
+            sl.sig_n = (uint32_t)n;
+        }
+        hipError_t e = hipGraphLaunch(sl.exec, stream);
+        if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+    } else {
+        rc = enqueue_tiled_batch(sl, L, (char *)ws, (uint32_t)n, (uint32_t)total_units, stream);
+        if (rc != CFAR_OK) return rc;
+    }
+    hipError_t e = hipEventRecord(sl.done, stream);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+    sl.recorded = true;
+    return CFAR_OK;
+}
+
+// Single map, TILED: descriptor travels as a kernel argument; ws holds the
+// work counter and the threshold table.
+static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    Plan p;
+    if (!plan_geometry(m, cp.k_cols, cp.rows_per_unit, &p)) return set_error(CFAR_EINVAL, "no valid tile plan");
+    const size_t need = 256 + lut_bytes(m);
+    if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
+    if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
+    const uint64_t units = units_of(p);
+    if (units >= (uint64_t)1 << 31) return set_error(CFAR_EINVAL, "map has too many work units");
+    uint32_t *counter = (uint32_t *)ws;
+    double *lut = (double *)((char *)ws + 256);
+    FusedArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.single = make_desc(m, &p, lut);
+    a.counter = counter;
+    a.total_units = (uint32_t)units;
+    a.n_maps = 1;
+    hipError_t e = launch_lut(nullptr, a.single, 1, counter, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
+    e = launch_fused(a, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
+    return CFAR_OK;
+}
+
+// Single map, PLAIN: FP64 SAT into ws, table, stencil.
+static int run_plain_single(const cfar_map *m, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    const size_t need = plain_single_ws(m);
+    if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
+    if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
+    char *base = (char *)ws;
+    const size_t sat_b = align_up((size_t)m->rows * (size_t)m->cols * 8, 256);
+    double *sat = (double *)base;
+    SatWs sw = sat_ws_layout(base + sat_b, m->rows, m->cols);
+    double *lut = (double *)(base + sat_b + sat_ws_bytes(m->rows, m->cols));
+    hipError_t e = launch_sat2d(m->x, m->dtype, m->rows, m->cols, m->ld, 0, sat, sw, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(sat2d)");
+    MapDesc d = make_desc(m, nullptr, lut);
+    e = launch_lut(nullptr, d, 1, nullptr, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
+    e = launch_stencil_plain(d, sat, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(stencil_plain)");
+    return CFAR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// SAT workspace
+// ---------------------------------------------------------------------------
+size_t sat_ws_bytes(int64_t rows, int64_t cols)
+{
+    const int64_t nI = (rows + kSatTH - 1) / kSatTH, nJ = (cols + kSatTW - 1) / kSatTW;
+    const size_t t = (size_t)(nI * nJ);
+    return align_up(t * kSatTH * 8, 256) * 2 + align_up(t * kSatTW * 8, 256) * 2 + align_up(t * 8, 256) * 2;
+}
+
+SatWs sat_ws_layout(void *ws, int64_t rows, int64_t cols)
+{
+    SatWs s;
+    s.nI = (rows + kSatTH - 1) / kSatTH;
+    s.nJ = (cols + kSatTW - 1) / kSatTW;
+    const size_t t = (size_t)(s.nI * s.nJ);
+    char *p = (char *)ws;
+    s.agg_row = (double *)p; p += align_up(t * kSatTH * 8, 256);
+    s.left = (double *)p; p += align_up(t * kSatTH * 8, 256);
+    s.agg_cs = (double *)p; p += align_up(t * kSatTW * 8, 256);
+    s.top = (double *)p; p += align_up(t * kSatTW * 8, 256);
+    s.agg_tot = (double *)p; p += align_up(t * 8, 256);
+    s.rt = (double *)p;
+    return s;
+}
+
+}  // namespace cfar
+
+using namespace cfar;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *cfar_last_error(void) { return g_err.c_str(); }
+
+const char *cfar_version(void) { return "cfar2d-mi355x 0.1 (gfx950)"; }
+
+size_t sat2d_bytes(int64_t rows, int64_t cols, int32_t form)
+{
+    if (rows < 1 || cols < 1 || rows > kMaxDim || cols > kMaxDim) return 0;
+    if (form == CFAR_FORM_PLAIN) return (size_t)rows * (size_t)cols * 8;
+    if (form == CFAR_FORM_TILED) {
+        const int64_t nI32 = (rows + kLine - 1) / kLine, nJ32 = (cols + kLine - 1) / kLine;
+        return align_up((size_t)rows * cols * 4, 256) + align_up((size_t)nI32 * cols * 8, 256) +
+               align_up((size_t)nJ32 * rows * 8, 256);
+    }
+    return 0;
+}
+
+size_t sat2d_workspace_bytes(int64_t rows, int64_t cols, int32_t form)
+{
+    if (rows < 1 || cols < 1 || rows > kMaxDim || cols > kMaxDim) return 0;
+    if (form != CFAR_FORM_PLAIN && form != CFAR_FORM_TILED) return 0;
+    return sat_ws_bytes(rows, cols);
+}
+
+int sat2d(const void *x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, int32_t form, void *sat_out,
+          size_t sat_bytes, void *ws, size_t ws_bytes, void *stream)
+{
+    if (dtype != CFAR_F32 && dtype != CFAR_F64) return set_error(CFAR_EINVAL, "unknown dtype %d", dtype);
+    if (form != CFAR_FORM_PLAIN && form != CFAR_FORM_TILED) return set_error(CFAR_EINVAL, "unknown form %d", form);
+    if (rows < 1 || cols < 1 || rows > kMaxDim || cols > kMaxDim)
+        return set_error(CFAR_EINVAL, "rows and cols must lie in [1, 2^30]");
+    if (ld < cols) return set_error(CFAR_EINVAL, "ld < cols");
+    if (!x || !sat_out || !ws) return set_error(CFAR_EINVAL, "NULL pointer argument");
+    const size_t need = sat2d_bytes(rows, cols, form);
+    if (sat_bytes < need) return set_error(CFAR_ENOSPC, "sat_bytes %zu < %zu needed", sat_bytes, need);
+    const size_t wneed = sat_ws_bytes(rows, cols);
+    if (ws_bytes < wneed) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, wneed);
+    SatWs sw = sat_ws_layout(ws, rows, cols);
+    hipError_t e = launch_sat2d(x, dtype, rows, cols, ld, form, sat_out, sw, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "launch(sat2d)");
+    return CFAR_OK;
+}
+
+size_t cfar_workspace_bytes(const cfar_map *maps, int32_t n, int32_t form)
+{
+    if (!maps || n < 1) { set_error(CFAR_EINVAL, "maps is NULL or n < 1"); return 0; }
+    for (int i = 0; i < n; ++i)
+        if (validate_map(&maps[i], i, form) != CFAR_OK) return 0;
+    if (form == CFAR_FORM_PLAIN) {
+        size_t need = 0;
+        for (int i = 0; i < n; ++i) need = std::max(need, plain_single_ws(&maps[i]));
+        return need;
+    }
+    uint64_t total_units = 0;
+    for (int i = 0; i < n; ++i) {
+        cfar_plan cp = choose_plan(&maps[i]);
+        Plan p;
+        if (!plan_geometry(&maps[i], cp.k_cols, cp.rows_per_unit, &p)) return 0;
+        total_units += units_of(p);
+    }
+    // enough for the batch layout; a single map needs less
+    return tiled_layout(maps, n, total_units).total;
+}
+
+int cfar2d(const cfar_map *m, int32_t form, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = validate_map(m, 0, form);
+    if (rc != CFAR_OK) return rc;
+    if (form == CFAR_FORM_PLAIN) return run_plain_single(m, ws, ws_bytes, (hipStream_t)stream);
+    return run_tiled_single(m, choose_plan(m), ws, ws_bytes, (hipStream_t)stream);
+}
+
+int cfar2d_with_plan(const cfar_map *m, const cfar_plan *plan, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = validate_map(m, 0, CFAR_FORM_TILED);
+    if (rc != CFAR_OK) return rc;
+    if (!plan || !plan_valid(m, plan)) return set_error(CFAR_EINVAL, "invalid plan for this map");
+    return run_tiled_single(m, *plan, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags, void *ws, size_t ws_bytes,
+                   void *stream)
+{
+    if (!maps || n < 1) return set_error(CFAR_EINVAL, "maps is NULL or n < 1");
+    if (flags & ~CFAR_BATCH_GRAPH) return set_error(CFAR_EINVAL, "unknown flags 0x%x", flags);
+    for (int i = 0; i < n; ++i) {
+        int rc = validate_map(&maps[i], i, form);
+        if (rc != CFAR_OK) return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (form == CFAR_FORM_PLAIN) {
+        size_t need = 0;
+        for (int i = 0; i < n; ++i) need = std::max(need, plain_single_ws(&maps[i]));
+        if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
+        for (int i = 0; i < n; ++i) {
+            int rc = run_plain_single(&maps[i], ws, ws_bytes, s);
+            if (rc != CFAR_OK) return rc;
+        }
+        return CFAR_OK;
+    }
+    return run_tiled_batch(maps, n, flags, ws, ws_bytes, s, nullptr);
+}
+
+int cfar_plan_for(const cfar_map *m, cfar_plan *out)
+{
+    int rc = validate_map(m, 0, CFAR_FORM_TILED);
+    if (rc != CFAR_OK) return rc;
+    if (!out) return set_error(CFAR_EINVAL, "out is NULL");
+    *out = choose_plan(m);
+    return CFAR_OK;
+}
+
+// Plan table: one rule per line,
+//   dtype cols_lo cols_hi rows_lo rows_hi hf_lo hf_hi hr_lo hr_hi k rows_per_unit
+// dtype = f32 | f64 | any; '#' starts a comment.  First matching rule wins.
+int cfar_plan_load(const char *path)
+{
+    std::vector<PlanRule> rules;
+    if (path && *path) {
+        std::ifstream f(path);
+        if (!f) return set_error(CFAR_EINVAL, "cannot open plan table %s", path);
+        std::string line;
+        int ln = 0;
+        while (std::getline(f, line)) {
+            ++ln;
+            const size_t hash = line.find('#');
+            if (hash != std::string::npos) line.resize(hash);
+            std::istringstream is(line);
+            std::string dt;
+            if (!(is >> dt)) continue;
+            PlanRule r;
+            long long c0, c1, r0, r1;
+            if (!(is >> c0 >> c1 >> r0 >> r1 >> r.hf_lo >> r.hf_hi >> r.hr_lo >> r.hr_hi >> r.k >> r.rs))
+                return set_error(CFAR_EINVAL, "%s:%d: malformed rule", path, ln);
+            r.c_lo = c0; r.c_hi = c1; r.r_lo = r0; r.r_hi = r1;
+            if (dt == "f32") r.dtype = 0;
+            else if (dt == "f64") r.dtype = 1;
+            else if (dt == "any") r.dtype = -1;
+            else return set_error(CFAR_EINVAL, "%s:%d: dtype must be f32, f64 or any", path, ln);
+            if (!(r.k == 2 || r.k == 4 || r.k == 8) || r.rs < 1 || r.rs > 4096)
+                return set_error(CFAR_EINVAL, "%s:%d: k must be 2, 4 or 8 and rows_per_unit in [1, 4096]", path, ln);
+            rules.push_back(r);
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_rules.swap(rules);
+    return CFAR_OK;
+}
+
+}  // extern "C"

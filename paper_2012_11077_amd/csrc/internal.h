@@ -1,0 +1,114 @@
+// Internal declarations shared by the host code and the HIP kernels of
+// libcfar2d.so.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace cfar {
+
+// ---------------------------------------------------------------------------
+// One map as the device sees it.  Built on the host from a cfar_map plus the
+// tile plan; 128 bytes so an array of them packs on 128-byte boundaries.
+// ---------------------------------------------------------------------------
+struct MapDesc {
+    const void *x;        // map, rows x cols, leading dimension ld
+    uint8_t *mask;        // rows x cols, leading dimension ld_mask
+    double *train_sum;    // optional
+    double *thresh;       // optional
+    double *lut;          // lut[n] = expm1(-ln(pfa)/n) = alpha(n)/n for n = 1..n_full
+    int64_t ld;
+    int64_t ld_mask;
+    double neg_log_pfa;   // -ln(pfa)
+    int32_t rows, cols;
+    int32_t gr, gf;       // guard half-widths
+    int32_t hr, hf;       // outer half-widths (guard + train)
+    int32_t dtype;        // 0 = f32, 1 = f64
+    int32_t k_cols;       // TILED: columns per lane (2, 4, 8)
+    int32_t rs;           // TILED: output rows per work unit
+    int32_t halo_f;       // TILED: column halo, >= hf, multiple of 4
+    int32_t tw;           // TILED: output columns per strip = 64*k_cols - 2*halo_f
+    int32_t n_strips;     // TILED: strips across the columns
+    int32_t n_rchunks;    // TILED: row chunks
+    int32_t n_full;       // training cells of an unclipped window
+    int32_t vec_ok;       // 1: x rows and mask rows allow aligned vector access
+    int32_t pad0;
+};
+static_assert(sizeof(MapDesc) == 128, "MapDesc must stay 128 bytes");
+
+// Arguments of the persistent TILED kernel.  When descs == nullptr the kernel
+// works on the single map in `single` (no device-side descriptor table).
+struct FusedArgs {
+    const MapDesc *descs;      // n_maps descriptors in device memory, or nullptr
+    const uint32_t *unit_map;  // map index of every work unit (device), or nullptr
+    const uint32_t *unit_base; // first work unit of every map (device), or nullptr
+    uint32_t *counter;         // work counter (device), zeroed by the table kernel
+    uint32_t total_units;
+    uint32_t n_maps;
+    MapDesc single;
+};
+
+// Layout of the TILED batch workspace.  The host writes the first part
+// (header + descriptors + unit tables) with one host-to-device copy; the
+// threshold tables that follow are filled on the device.
+struct BatchHeader {
+    uint32_t counter;
+    uint32_t n_maps;
+    uint32_t total_units;
+    uint32_t pad[61];
+};
+static_assert(sizeof(BatchHeader) == 256, "BatchHeader must stay 256 bytes");
+
+// SAT tile geometry of the PLAIN form: 32 rows x 256 columns per workgroup.
+constexpr int kSatTH = 32;
+constexpr int kSatTW = 256;
+// Line spacing of the TILED sat2d layout (FP32 local tiles of 32 x 32).
+constexpr int kLine = 32;
+
+// Work areas of sat2d inside its workspace (element offsets computed by
+// sat_ws_layout on the host).
+struct SatWs {
+    double *agg_row;   // [nI][nJ][32]  row sums of every tile
+    double *agg_cs;    // [nI][nJ][256] local integral image, last row, of every tile
+    double *agg_tot;   // [nI][nJ]      tile totals
+    double *left;      // [nI][nJ][32]  sum of X left of the tile, per row
+    double *rt;        // [nI][nJ]      sum of tile totals left of the tile (same tile row)
+    double *top;       // [nI][nJ][256] S(r0 - 1, j) above the tile
+    int64_t nI, nJ;
+};
+
+size_t sat_ws_bytes(int64_t rows, int64_t cols);
+SatWs sat_ws_layout(void *ws, int64_t rows, int64_t cols);
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).  All enqueue on `stream` and return the
+// hipError_t of the launch.
+// ---------------------------------------------------------------------------
+
+// PLAIN / TILED integral image.  out_form 0: FP64 SAT at `sat` (ld = cols).
+// out_form 1: TILED layout at `sat` (see cfar2d.h).
+hipError_t launch_sat2d(const void *x, int dtype, int64_t rows, int64_t cols, int64_t ld,
+                        int out_form, void *sat, const SatWs &ws, hipStream_t stream);
+
+// Threshold tables (and the work counter) for `n` maps.  descs: device
+// descriptor table, or nullptr with `single` used instead.
+hipError_t launch_lut(const MapDesc *descs, const MapDesc &single, int n, uint32_t *counter,
+                      hipStream_t stream);
+
+// Eight-corner stencil over the PLAIN FP64 SAT of one map.
+hipError_t launch_stencil_plain(const MapDesc &d, const double *sat, hipStream_t stream);
+
+// Persistent TILED kernel over all work units in `args`.
+hipError_t launch_fused(const FusedArgs &args, hipStream_t stream);
+
+// Number of persistent workgroups of the TILED kernel that fit the device.
+int fused_resident_blocks();
+
+constexpr int kFusedThreads = 256;  // 4 independent waves per workgroup
+constexpr int kMaxK = 8;
+
+}  // namespace cfar

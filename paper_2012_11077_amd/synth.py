@@ -80,6 +80,12 @@ def _clutter_mean(spec: MapSpec, i: np.ndarray) -> np.ndarray:
 
 def generate(spec: MapSpec, out: Optional[np.ndarray] = None) -> np.ndarray:
     """Draw the map described by ``spec`` (C-contiguous, rows x cols, spec.dtype)."""
+    return generate_with_targets(spec, out)[0]
+
+
+def generate_with_targets(spec: MapSpec, out: Optional[np.ndarray] = None):
+    """Draw the map and return ``(map, targets)``, targets an (n, 3) array of
+    (row, col, snr_db) of the planted point targets."""
     dt = DTYPES[spec.dtype]
     rng = _rng(spec.seed)
     R, F = spec.rows, spec.cols
@@ -100,6 +106,7 @@ def generate(spec: MapSpec, out: Optional[np.ndarray] = None) -> np.ndarray:
     else:
         raise ValueError("unknown clutter model %r" % spec.clutter)
     n = spec.n_targets
+    targets = np.zeros((0, 3))
     if n > 0:
         ti = rng.integers(0, R, size=n)
         tj = rng.integers(0, F, size=n)
@@ -116,7 +123,8 @@ def generate(spec: MapSpec, out: Optional[np.ndarray] = None) -> np.ndarray:
                     if b < 0 or b >= F:
                         continue
                     out[a, b] += dt(amp[k] * w[di + 1] * w[dj + 1])
-    return out
+        targets = np.stack([ti.astype(np.float64), tj.astype(np.float64), snr], axis=1)
+    return out, targets
 
 
 # ---------------------------------------------------------------------------

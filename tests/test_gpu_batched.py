@@ -1,0 +1,132 @@
+"""Batched CA-CFAR through the C ABI: parity per map, the same result alone
+and in any batch, graph replay, and the plain per-map form."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2012_11077_amd import cfar2d as C
+from paper_2012_11077_amd import synth
+from parity import check_full, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _small_batch(n=24, seed=3):
+    specs = synth.config3_specs(n=n, seed=seed, rows=(20, 300), cols=(8, 300))
+    xs_np = [synth.generate(s) for s in specs]
+    return specs, xs_np
+
+
+def _alloc(xs):
+    masks = [torch.empty(x.shape, dtype=torch.uint8, device=DEV) for x in xs]
+    sts = [torch.empty(x.shape, dtype=torch.float64, device=DEV) for x in xs]
+    return masks, sts
+
+
+@pytest.mark.parametrize("form", ["tiled", "plain"])
+@pytest.mark.parametrize("flags", [0, C.BATCH_GRAPH])
+def test_batched_parity(form, flags):
+    specs, xs_np = _small_batch()
+    xs = [torch.from_numpy(x).to(DEV) for x in xs_np]
+    masks, sts = _alloc(xs)
+    say("batched", form, flags, len(xs))
+    C.cfar2d_batched(xs, [s.window for s in specs], C.TILED if form == "tiled" else C.PLAIN,
+                     masks=masks, train_sums=sts, flags=flags)
+    torch.cuda.synchronize()
+    for k, s in enumerate(specs):
+        check_full(xs_np[k], s.window, masks[k].cpu().numpy(), sts[k].cpu().numpy(), None, form)
+
+
+def test_alone_equals_in_mix_and_order_free():
+    specs, xs_np = _small_batch(n=20, seed=5)
+    xs = [torch.from_numpy(x).to(DEV) for x in xs_np]
+    wins = [s.window for s in specs]
+    masks, sts = _alloc(xs)
+    C.cfar2d_batched(xs, wins, C.TILED, masks=masks, train_sums=sts)
+    torch.cuda.synchronize()
+    batch = [(m.cpu().numpy(), s.cpu().numpy()) for m, s in zip(masks, sts)]
+    # alone
+    for k in range(len(xs)):
+        m = torch.empty(xs[k].shape, dtype=torch.uint8, device=DEV)
+        s = torch.empty(xs[k].shape, dtype=torch.float64, device=DEV)
+        C.cfar2d(xs[k], wins[k], C.TILED, mask=m, train_sum=s)
+        torch.cuda.synchronize()
+        assert np.array_equal(m.cpu().numpy(), batch[k][0])
+        assert np.array_equal(s.cpu().numpy().view(np.int64), batch[k][1].view(np.int64))
+    # reversed order, and mixed with other maps
+    perm = list(reversed(range(len(xs))))
+    extra_specs, extra_np = _small_batch(n=6, seed=9)
+    xs2 = [xs[p] for p in perm] + [torch.from_numpy(x).to(DEV) for x in extra_np]
+    wins2 = [wins[p] for p in perm] + [s.window for s in extra_specs]
+    masks2, sts2 = _alloc(xs2)
+    C.cfar2d_batched(xs2, wins2, C.TILED, masks=masks2, train_sums=sts2)
+    torch.cuda.synchronize()
+    for i, p in enumerate(perm):
+        assert np.array_equal(masks2[i].cpu().numpy(), batch[p][0])
+        assert np.array_equal(sts2[i].cpu().numpy().view(np.int64), batch[p][1].view(np.int64))
+
+
+def test_graph_replays_match_eager():
+    """Replay the captured batch several times on a side stream with other
+    work and synchronisations between replays; every replay equals the eager
+    result, also after the inputs change in place."""
+    specs, xs_np = _small_batch(n=16, seed=7)
+    xs = [torch.from_numpy(x).to(DEV) for x in xs_np]
+    wins = [s.window for s in specs]
+    eager_masks, eager_sts = _alloc(xs)
+    C.cfar2d_batched(xs, wins, C.TILED, masks=eager_masks, train_sums=eager_sts, flags=0)
+    torch.cuda.synchronize()
+    ref = [(m.cpu().numpy(), s.cpu().numpy()) for m, s in zip(eager_masks, eager_sts)]
+    side = torch.cuda.Stream()
+    masks, sts = _alloc(xs)
+    b = C.Batch(xs, wins, C.TILED, masks=masks, train_sums=sts)
+    for rep in range(5):
+        for m in masks:
+            m.fill_(7)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            b.run(C.BATCH_GRAPH, stream=side)
+        side.synchronize()
+        junk = torch.randn(1000, 1000, device=DEV) @ torch.randn(1000, 1000, device=DEV)
+        torch.cuda.synchronize()
+        del junk
+        for k in range(len(xs)):
+            assert np.array_equal(masks[k].cpu().numpy(), ref[k][0]), (rep, k)
+            assert np.array_equal(sts[k].cpu().numpy(), ref[k][1]), (rep, k)
+    # change the data in place: the replay must pick up the new values
+    for x in xs:
+        x.mul_(2.0)
+    with torch.cuda.stream(side):
+        b.run(C.BATCH_GRAPH, stream=side)
+    side.synchronize()
+    for k in range(len(xs)):
+        assert np.array_equal(masks[k].cpu().numpy(), ref[k][0])
+        np.testing.assert_array_equal(sts[k].cpu().numpy(), 2.0 * ref[k][1])
+
+
+def test_batched_full_config_sampled():
+    """The full uneven batch in the benchmark's launch configuration (one
+    persistent launch, graph replay), checked on sampled cells of a subset
+    of maps against the oracle's direct sums."""
+    import oracle
+    from parity import check_cells, sample_cells
+    specs = synth.config3_specs()
+    xs = []
+    say("full batch: generating", len(specs), "maps")
+    for s in specs:
+        xs.append(torch.from_numpy(synth.generate(s)).to(DEV))
+    masks = [torch.empty(x.shape, dtype=torch.uint8, device=DEV) for x in xs]
+    b = C.Batch(xs, [s.window for s in specs], C.TILED, masks=masks)
+    for _ in range(2):
+        b.run(C.BATCH_GRAPH)
+    torch.cuda.synchronize()
+    say("full batch: checking")
+    rng = np.random.default_rng(0)
+    for k in rng.choice(len(specs), 24, replace=False):
+        s = specs[k]
+        x_np, tg = synth.generate_with_targets(s)
+        rows, cols = sample_cells(s.rows, s.cols, s.guard_r + s.train_r, s.guard_f + s.train_f, tg,
+                                  n_random=3000, seed=int(k))
+        m = masks[k].cpu().numpy()
+        check_cells(x_np, s.window, rows, cols, m[rows, cols])

@@ -1,0 +1,174 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Sizes the oracle finishes in seconds (several tiles and ragged tails), the
+edge cases of the method (1x1 maps, windows wider than the map, zero guard
+or zero training on one axis, strided and misaligned maps), and the full
+benchmark sizes checked on sampled cells against the oracle's direct sums.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2012_11077_amd import cfar2d as C
+from paper_2012_11077_amd import synth
+from parity import check_cells, check_full, sample_cells, say
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+FORMS = {"plain": C.PLAIN, "tiled": C.TILED}
+
+
+def _run(x_np, window, form, with_outputs=True, x_dev=None):
+    x = x_dev if x_dev is not None else torch.from_numpy(x_np).to(DEV)
+    R, F = x.shape
+    mask = torch.empty((R, F), dtype=torch.uint8, device=DEV)
+    st = torch.empty((R, F), dtype=torch.float64, device=DEV) if with_outputs else None
+    th = torch.empty((R, F), dtype=torch.float64, device=DEV) if with_outputs else None
+    C.cfar2d(x, window, FORMS[form], mask=mask, train_sum=st, threshold=th)
+    torch.cuda.synchronize()
+    return (mask.cpu().numpy(), st.cpu().numpy() if st is not None else None,
+            th.cpu().numpy() if th is not None else None)
+
+
+@pytest.mark.parametrize("form", ["plain", "tiled"])
+def test_config0(form):
+    spec = synth.config0()
+    x, targets = synth.generate_with_targets(spec)
+    say("config0", form, spec.rows, spec.cols)
+    mask, st, th = _run(x, spec.window, form)
+    r = check_full(x, spec.window, mask, st, th, form)
+    say("config0", form, r)
+    for t in targets:   # 15 dB targets on Exp(1) clutter are found by both
+        assert mask[int(t[0]), int(t[1])] == 1
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("form", ["plain", "tiled"])
+def test_random_small_maps(form, dtype):
+    specs = synth.random_small_specs(40, seed=11 if dtype == "f32" else 12, dtype=dtype)
+    for k, spec in enumerate(specs):
+        x = synth.generate(spec)
+        say("random", form, dtype, k, spec.rows, spec.cols, spec.window)
+        mask, st, th = _run(x, spec.window, form)
+        check_full(x, spec.window, mask, st, th, form)
+
+
+EDGE = [
+    # rows, cols, gr, gf, tr, tf, pfa
+    (1, 1, 0, 0, 1, 1, 0.5),
+    (1, 300, 0, 2, 3, 9, 1e-2),
+    (300, 1, 2, 0, 9, 3, 1e-2),
+    (3, 3, 4, 4, 4, 4, 1e-3),
+    (5, 700, 1, 1, 0, 6, 1e-3),        # no training along rows
+    (700, 5, 1, 1, 6, 0, 1e-3),        # no training along columns
+    (97, 131, 0, 0, 5, 5, 1e-4),       # no guard
+    (64, 400, 4, 4, 24, 24, 1e-5),
+    (40, 1100, 2, 10, 3, 240, 1e-4),   # column half-width near the TILED limit
+    (130, 520, 1, 0, 2, 250, 1e-3),    # hf = 250
+    (256, 456, 4, 4, 24, 24, 1e-5),    # exactly one strip wide at k = 8
+    (513, 457, 3, 3, 16, 16, 1e-6),    # ragged tails
+]
+
+
+@pytest.mark.parametrize("form", ["plain", "tiled"])
+@pytest.mark.parametrize("case", EDGE, ids=[str(c[:2] + c[2:6]) for c in EDGE])
+def test_edge_shapes(form, case):
+    R, F, gr, gf, tr, tf, pfa = case
+    spec = synth.MapSpec(R, F, "f32", "exp", 2.0, n_targets=3, guard_r=gr, guard_f=gf, train_r=tr,
+                         train_f=tf, pfa=pfa, seed=(5, R, F))
+    x = synth.generate(spec)
+    say("edge", form, case)
+    mask, st, th = _run(x, spec.window, form)
+    check_full(x, spec.window, mask, st, th, form)
+
+
+@pytest.mark.parametrize("form", ["plain", "tiled"])
+def test_strided_and_misaligned(form):
+    """ld > cols, ld_mask > cols and a map pointer that is not 16-byte
+    aligned (vector paths must fall back)."""
+    rng = np.random.default_rng(3)
+    R, F = 150, 333
+    big = torch.from_numpy(rng.exponential(1.0, size=(R, F + 9)).astype(np.float32)).to(DEV)
+    win = (2, 3, 7, 11, 1e-3)
+    for off in (0, 1, 3):
+        xv = big[:, off:off + F]
+        mbig = torch.zeros((R, F + 5), dtype=torch.uint8, device=DEV)
+        mv = mbig[:, 1:F + 1] if off else mbig[:, :F]
+        say("strided", form, off)
+        C.cfar2d(xv, win, FORMS[form], mask=mv)
+        torch.cuda.synchronize()
+        x_np = xv.cpu().numpy()
+        check_full(x_np, win, mv.cpu().numpy())
+        # columns outside the view are untouched
+        assert int(mbig[:, F + 1:].sum().item()) == 0
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_sat2d_plain(dtype):
+    rng = np.random.default_rng(7)
+    for R, F in [(1, 1), (31, 257), (200, 700), (1000, 513)]:
+        x = rng.lognormal(0.0, 1.0, size=(R, F)).astype(np.float32 if dtype == "f32" else np.float64)
+        say("sat2d plain", dtype, R, F)
+        S = C.sat2d(torch.from_numpy(x).to(DEV), C.PLAIN)
+        torch.cuda.synchronize()
+        ref = oracle.sat(x)[1:, 1:]
+        np.testing.assert_allclose(S.cpu().numpy(), ref, rtol=1e-12, atol=0)
+
+
+def test_sat2d_plain_integer_exact():
+    rng = np.random.default_rng(8)
+    x = rng.integers(0, 256, size=(777, 1029)).astype(np.float32)
+    S = C.sat2d(torch.from_numpy(x).to(DEV), C.PLAIN)
+    torch.cuda.synchronize()
+    assert np.array_equal(S.cpu().numpy(), oracle.sat(x)[1:, 1:])
+
+
+def test_sat2d_tiled_layout():
+    rng = np.random.default_rng(9)
+    for R, F in [(1, 1), (33, 65), (300, 500)]:
+        x = rng.lognormal(0.0, 1.0, size=(R, F)).astype(np.float32)
+        say("sat2d tiled", R, F)
+        buf = C.sat2d(torch.from_numpy(x).to(DEV), C.TILED)
+        torch.cuda.synchronize()
+        S = C.decode_tiled_sat(buf, R, F).cpu().numpy()
+        ref = oracle.sat(x)[1:, 1:]
+        # FP32 local sums hold at most 32 x 32 cells: error within a few
+        # FP32 ulps of the local sum, far below the SAT entries themselves
+        np.testing.assert_allclose(S, ref, rtol=1e-6, atol=0)
+        # the local region itself: integer maps decode exactly
+    xi = rng.integers(0, 64, size=(97, 131)).astype(np.float32)
+    buf = C.sat2d(torch.from_numpy(xi).to(DEV), C.TILED)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.decode_tiled_sat(buf, 97, 131).cpu().numpy(), oracle.sat(xi)[1:, 1:])
+
+
+def test_repeat_is_bitwise_deterministic():
+    spec = synth.config2(1024, 1024)
+    x = torch.from_numpy(synth.generate(spec)).to(DEV)
+    outs = []
+    for _ in range(3):
+        mask = torch.empty(x.shape, dtype=torch.uint8, device=DEV)
+        st = torch.empty(x.shape, dtype=torch.float64, device=DEV)
+        C.cfar2d(x, spec.window, C.TILED, mask=mask, train_sum=st)
+        torch.cuda.synchronize()
+        outs.append((mask.cpu().numpy(), st.cpu().numpy()))
+    for m, s in outs[1:]:
+        assert np.array_equal(m, outs[0][0]) and np.array_equal(s.view(np.int64), outs[0][1].view(np.int64))
+
+
+def test_plans_give_the_same_answer():
+    """Every tile plan computes the same detector (within the parity rule)."""
+    spec = synth.config2(700, 900)
+    x_np = synth.generate(spec)
+    x = torch.from_numpy(x_np).to(DEV)
+    ref = oracle.cfar2d(x_np, *spec.window)
+    for k in (2, 4, 8):
+        for rs in (1, 7, 64, 700):
+            mask = torch.empty(x.shape, dtype=torch.uint8, device=DEV)
+            st = torch.empty(x.shape, dtype=torch.float64, device=DEV)
+            say("plan", k, rs)
+            C.cfar2d_with_plan(x, spec.window, k, rs, mask=mask, train_sum=st)
+            torch.cuda.synchronize()
+            check_full(x_np, spec.window, mask.cpu().numpy(), st.cpu().numpy(), None, "tiled", ref=ref)
