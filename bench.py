@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark of integral-image 2D CA-CFAR on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--gpus 1]
+
+A step is one pass of the whole hot path over one batch of synthetic input:
+threshold tables, then the fused tiled CA-CFAR (tile-local prefix sums with
+FP64 carries, eight corners, threshold, decision) over every map, as one
+persistent launch replayed from a captured hipGraph.  Inputs are resident in
+device memory before the timed region starts.
+
+Default workload: the uneven batch of 512 FP32 maps (rows U[200, 4096] x
+cols U[64, 2048], per-map window and Pfa).  Beside it the same maps go
+through the plain per-map FP64 form (FP64 integral image in device memory,
+then the eight-corner stencil, one map after the other) and the CPU oracle
+is timed on a bounded sample of the maps.
+
+Prints ONE JSON line.  ``value`` is cells/s of the chosen (tiled) form;
+``roofline`` prices the dominant kernel (the persistent CA-CFAR kernel) at
+its algorithmic bytes (map read once + mask written once) against HBM peak.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "CA-CFAR cells/s & % HBM peak, chosen vs plain form at equal mask; p99 latency"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_kernel_uneven_batch_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    p = os.path.join(ROOT, "paper_2012_11077_amd", "csrc", "kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_source_sha():
+        return None
+    return t
+
+
+def percentile(v, q):
+    v = sorted(v)
+    if not v:
+        return None
+    k = min(len(v) - 1, max(0, int(math.ceil(q / 100.0 * len(v))) - 1))
+    return v[k]
+
+
+def cpu_baseline(specs, arrays, budget_s=12.0):
+    """The FP64 oracle (single thread, as it stands) on the first maps of the
+    batch until about budget_s of CPU work; cells/s over that sample."""
+    import oracle
+    oracle.build(force=False)
+    cells, t_tot, n = 0, 0.0, 0
+    for s, x in zip(specs, arrays):
+        t0 = time.perf_counter()
+        oracle.cfar2d(x, *s.window)
+        t_tot += time.perf_counter() - t0
+        cells += s.cells
+        n += 1
+        if t_tot >= budget_s:
+            break
+    return {"value": cells / t_tot, "unit": "cells/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d maps of the workload (%d cells), oracle FP64 single thread, %.1f s"
+                      % (n, len(specs), cells, t_tot)}
+
+
+def build_workload(name):
+    from paper_2012_11077_amd import synth
+    if name == "batched":
+        specs = synth.config3_specs()
+        desc = ("uneven batch: 512 FP32 maps, rows U[200,4096] x cols U[64,2048], Exp clutter mean "
+                "log-U[0.1,10], 0-20 targets at 10-25 dB, guard 1-4 and training 4-24 per axis, "
+                "Pfa in {1e-3,1e-4,1e-6}, seed 3")
+    elif name == "precision":
+        specs = [synth.config2()]
+        desc = ("one 16384x16384 FP32 map, log-normal clutter sigma 2, 1000 targets at 8-30 dB, "
+                "guard 4x4, training 24x24, Pfa 1e-5, seed 2")
+    elif name == "plain_scale":
+        specs = [synth.config1()]
+        desc = ("one 8192x8192 FP64 map, Exp clutter on a 0-20 dB range ramp, 200 targets at 10-25 dB, "
+                "guard 3x3, training 16x16, Pfa 1e-6, seed 1")
+    elif name == "small":
+        specs = [synth.config0()]
+        desc = "one 512x256 FP64 map, Exp(1) clutter, 5 targets at 15 dB, guard 2x2, training 8x8, Pfa 1e-4"
+    else:
+        raise SystemExit("unknown workload %r" % name)
+    return specs, desc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batched",
+                    choices=["batched", "precision", "plain_scale", "small"])
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup + steps of the tiled form only (for rocprofv3)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the workload would shard by map; see the design notes). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2012_11077_amd import cfar2d as C
+    from paper_2012_11077_amd import synth
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    C.lib()
+
+    specs, desc = build_workload(args.workload)
+    log("generating %d maps" % len(specs))
+    t0 = time.perf_counter()
+    arrays = [synth.generate(s) for s in specs]
+    xs = [torch.from_numpy(a).to(dev) for a in arrays]
+    torch.cuda.synchronize()
+    log("generated + uploaded in %.1f s" % (time.perf_counter() - t0))
+    cells = sum(s.cells for s in specs)
+    in_bytes = sum(a.nbytes for a in arrays)
+    elem = arrays[0].dtype.itemsize
+    wins = [s.window for s in specs]
+
+    # ---- chosen form: fused tiled, persistent launch, graph replay -------------
+    masks = [torch.empty(x.shape, dtype=torch.uint8, device=dev) for x in xs]
+    batch = C.Batch(xs, wins, C.TILED, masks=masks)
+    flags = 0 if args.no_graph else C.BATCH_GRAPH
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        batch.run(flags)
+    torch.cuda.synchronize()
+    log("timing %d steps" % args.steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(args.steps):
+        batch.run(flags)
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    ms_per_step = evs[0].elapsed_time(evs[-1]) / args.steps
+    value = cells / (ms_per_step / 1e3)
+    log("tiled: %.3f ms/step, %.3e cells/s (wall %.3f ms/step)" % (ms_per_step, value, wall / args.steps * 1e3))
+
+    if args.profile_only:
+        print(json.dumps({"profile_only": True, "ms_per_step": ms_per_step}))
+        return
+
+    # ---- dominant kernel alone: HIP events around the persistent kernel ----------
+    C.timing_enable(True)
+    kms = []
+    for _ in range(max(5, min(args.steps, 20))):
+        batch.run(0)
+        kms.append(C.timing_read())
+    C.timing_enable(False)
+    kernel_ms = float(np.mean(kms))
+    alg_bytes = in_bytes + cells  # map read once + uint8 mask written once
+    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "fused_kernel", "kernel_ms": round(kernel_ms, 4),
+            "alg_bytes_per_cell": round(alg_bytes / cells, 3)}
+    tr = measured_traffic()
+    if tr and tr.get("workload") == args.workload:
+        roof["traffic"] = tr["bytes_per_launch"]
+        roof["traffic_unit"] = "bytes/launch"
+        roof["traffic_per_cell"] = round(tr["bytes_per_launch"] / cells, 3)
+    log("kernel %.3f ms -> %.1f GB/s algorithmic (%.1f%% of HBM peak)" % (kernel_ms, achieved, 100 * achieved / HBM_PEAK_GBS))
+
+    # ---- plain per-map FP64 form on the same maps, compared at equal mask -------
+    plain = None
+    if not args.no_plain:
+        pmasks = [torch.empty(x.shape, dtype=torch.uint8, device=dev) for x in xs]
+        pbatch = C.Batch(xs, wins, C.PLAIN, masks=pmasks)
+        pbatch.run(0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.plain_steps):
+            pbatch.run(0)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / args.plain_steps
+        diff = sum(int((a != b).sum().item()) for a, b in zip(masks, pmasks))
+        plain = {"ms_per_step": round(pms, 3), "cells_per_s": cells / (pms / 1e3),
+                 "mask_cells_differing_from_tiled": diff}
+        log("plain: %.3f ms/step (%d mask cells differ from tiled)" % (pms, diff))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(specs, arrays)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "name": args.workload, "maps": len(specs), "cells": cells,
+                   "storage_dtype": str(arrays[0].dtype), "form": "tiled (fused, FP64 carries)",
+                   "graph": not args.no_graph, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4),
+                       "what": "per batched launch, back-to-back"},
+        "plain_form": plain,
+        "speedup_vs_plain": (round(plain["ms_per_step"] / ms_per_step, 3) if plain else None),
+        "effective_hbm_frac": round((in_bytes + cells) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

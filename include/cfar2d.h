@@ -239,6 +239,20 @@ int cfar_server_shutdown(cfar_server *s, int32_t drain_queued);
  * polled are dropped. */
 int cfar_server_destroy(cfar_server *s);
 
+/* ------------------------------------------------------------------------ */
+/* Kernel timing (benchmarks)                                                */
+/* ------------------------------------------------------------------------ */
+
+/* On the calling thread, on = 1 makes every following TILED launch
+ * (cfar2d, cfar2d_with_plan, cfar2d_batched) record a pair of HIP events
+ * on its stream right before and right after its persistent kernel; batches
+ * are then launched without graph capture.  on = 0 turns it off. */
+int cfar_timing_enable(int32_t on);
+
+/* Milliseconds between the two events of the calling thread's last timed
+ * launch (waits for it to finish).  CFAR_EINVAL if there was none. */
+int cfar_timing_read(double *kernel_ms);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *cfar_last_error(void);
 

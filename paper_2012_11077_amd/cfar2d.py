@@ -20,6 +20,9 @@ import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcfar2d.so")
+# Tile-plan table written by the autotuner (paper_2012_11077_amd/autotune.py);
+# CFAR2D_PLAN_TABLE overrides it ("" = the library's built-in cost model).
+DEFAULT_PLAN_TABLE = os.path.join(_PKG, "plan_table.txt")
 
 CFAR_OK, CFAR_EINVAL, CFAR_ENOSPC, CFAR_EDEVICE, CFAR_EAGAIN, CFAR_ESHUTDOWN = 0, -1, -2, -3, -4, -5
 F32, F64 = 0, 1
@@ -103,10 +106,17 @@ def lib():
             L.cfar_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
             L.cfar_server_shutdown.argtypes = [_vp, _i32]
             L.cfar_server_destroy.argtypes = [_vp]
+        L.cfar_timing_enable.argtypes = [_i32]
+        L.cfar_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
         for name in ("sat2d", "cfar2d", "cfar2d_batched", "cfar_plan_for", "cfar_plan_load",
-                     "cfar2d_with_plan"):
+                     "cfar2d_with_plan", "cfar_timing_enable", "cfar_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
+        table = os.environ.get("CFAR2D_PLAN_TABLE")
+        if table is None and os.path.exists(DEFAULT_PLAN_TABLE):
+            table = DEFAULT_PLAN_TABLE
+        if table:
+            _check(L.cfar_plan_load(table.encode()))
     return _lib
 
 
@@ -310,6 +320,18 @@ def plan_for(x: torch.Tensor, window) -> Tuple[int, int]:
 
 def _mask_like(x: torch.Tensor) -> torch.Tensor:
     return torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+
+
+def timing_enable(on: bool) -> None:
+    """Record HIP events around the persistent kernel of TILED launches (no graphs meanwhile)."""
+    _check(lib().cfar_timing_enable(1 if on else 0))
+
+
+def timing_read() -> float:
+    """Kernel milliseconds of the calling thread's last timed TILED launch."""
+    v = ctypes.c_double()
+    _check(lib().cfar_timing_read(ctypes.byref(v)))
+    return v.value
 
 
 def plan_load(path: Optional[str]) -> None:

@@ -43,11 +43,27 @@ int hip_error(hipError_t e, const char *what)
 }
 
 // ---------------------------------------------------------------------------
+// Kernel timing (thread-local): HIP events around the persistent kernel of
+// TILED launches that are not captured in a graph.
+// ---------------------------------------------------------------------------
+struct Timing {
+    bool on = false;
+    bool recorded = false;
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+static thread_local Timing g_timing;
+
+static hipError_t timing_mark(hipEvent_t ev, hipStream_t stream)
+{
+    return g_timing.on ? hipEventRecord(ev, stream) : hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
 // Validation
 // ---------------------------------------------------------------------------
 constexpr int64_t kMaxDim = int64_t(1) << 30;  // rows, cols
 constexpr int32_t kMaxHalf = 1024;             // any half-width
-constexpr int32_t kMaxTiledHf = 250;           // TILED: 64*8 columns per wave minus two halos
+constexpr int32_t kMaxTiledHf = 247;           // TILED: 64*8 columns per wave minus two halos
 
 int validate_map(const cfar_map *m, int idx, int form)
 {
@@ -97,7 +113,10 @@ struct Plan {
 static bool plan_geometry(const cfar_map *m, int k, int rs, Plan *p)
 {
     const int hf = m->win.guard_f + m->win.train_f;
-    const int H = (hf + 3) / 4 * 4;
+    // >= hf + 1 (every prefix read stays inside the strip) and a multiple of
+    // max(4, k) (lanes hold either k output columns or none)
+    const int a = k > 4 ? k : 4;
+    const int H = (hf + 1 + a - 1) / a * a;
     const int tw = 64 * k - 2 * H;
     if (tw < 4 || rs < 1) return false;
     p->k = k;
@@ -241,6 +260,15 @@ static TiledLayout tiled_layout(const cfar_map *maps, int n, uint64_t total_unit
     return L;
 }
 
+// Maps of one kernel class (columns per lane k, dtype) and their work units.
+struct KClass {
+    int k, dtype;
+    bool out;  // maps of the class may write the optional outputs
+    uint32_t unit_off, units, blocks;
+};
+static int class_slot(int k, int dtype, bool out) { return ((k == 2 ? 0 : k == 4 ? 1 : 2) * 2 + dtype) + (out ? 6 : 0); }
+static bool has_outputs(const cfar_map *m) { return m->train_sum != nullptr || m->threshold != nullptr; }
+
 static uint64_t units_of(const Plan &p) { return (uint64_t)p.n_strips * (uint64_t)p.n_rchunks; }
 
 // ---------------------------------------------------------------------------
@@ -256,7 +284,8 @@ struct Slot {
     hipGraph_t graph = nullptr;
     // signature of the captured graph
     size_t sig_head = 0;
-    uint32_t sig_units = 0, sig_blocks = 0, sig_n = 0;
+    uint64_t sig_layout = 0;
+    uint32_t sig_units = 0, sig_n = 0;
 };
 struct BatchCtx {
     Slot slot[2];
@@ -298,9 +327,9 @@ static int slot_reserve(Slot &sl, size_t bytes)
     return CFAR_OK;
 }
 
-// Enqueue: descriptor copy, table kernel, persistent kernel.
-static int enqueue_tiled_batch(const Slot &sl, const TiledLayout &L, char *ws, uint32_t n, uint32_t total_units,
-                               hipStream_t stream)
+// Enqueue: descriptor copy, table kernel, one persistent kernel per class.
+static int enqueue_tiled_batch(const Slot &sl, const TiledLayout &L, char *ws, uint32_t n,
+                               const std::vector<KClass> &classes, hipStream_t stream)
 {
     hipError_t e = hipMemcpyAsync(ws, sl.pinned, L.head_bytes, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(descriptors)");
@@ -308,18 +337,26 @@ static int enqueue_tiled_batch(const Slot &sl, const TiledLayout &L, char *ws, u
     std::memset(&dummy, 0, sizeof dummy);
     const MapDesc *descs = (const MapDesc *)(ws + L.off_desc);
     BatchHeader *hdr = (BatchHeader *)ws;
-    e = launch_lut(descs, dummy, (int)n, &hdr->counter, stream);
+    e = launch_lut(descs, dummy, (int)n, hdr->counter, stream);
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
-    FusedArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.descs = descs;
-    a.unit_base = (const uint32_t *)(ws + L.off_base);
-    a.unit_map = (const uint32_t *)(ws + L.off_umap);
-    a.counter = &hdr->counter;
-    a.total_units = total_units;
-    a.n_maps = n;
-    e = launch_fused(a, stream);
-    if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
+    e = timing_mark(g_timing.start, stream);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
+    for (const KClass &c : classes) {
+        FusedArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.descs = descs;
+        a.unit_base = (const uint32_t *)(ws + L.off_base);
+        a.unit_map = (const uint32_t *)(ws + L.off_umap) + c.unit_off;
+        a.counter = &hdr->counter[class_slot(c.k, c.dtype, c.out)];
+        a.sink = hdr->sink;
+        a.total_units = c.units;
+        a.n_maps = n;
+        e = launch_fused(a, c.k, c.dtype, c.out, stream);
+        if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
+    }
+    e = timing_mark(g_timing.stop, stream);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
+    if (g_timing.on) g_timing.recorded = true;
     return CFAR_OK;
 }
 
@@ -340,16 +377,45 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
         return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, L.total);
     if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
 
-    // Processing order: larger maps first (better tail balance).  A map's
-    // result does not depend on the order.
-    std::vector<int> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return units_of(plans[a]) > units_of(plans[b]); });
-
-    const int resident = fused_resident_blocks();
-    uint32_t blocks = (uint32_t)std::min<uint64_t>((total_units + 3) / 4, (uint64_t)resident);
-    if (blocks == 0) blocks = 1;
+    // Kernel classes (k, dtype), each with its own persistent launch; inside a
+    // class larger maps come first (better tail balance).  A map's result does
+    // not depend on the order or on the other maps.
+    std::vector<KClass> classes;
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < n; ++i) {
+        const int k = plans[i].k, dt = maps[i].dtype;
+        const bool out = has_outputs(&maps[i]);
+        size_t c = 0;
+        while (c < classes.size() && !(classes[c].k == k && classes[c].dtype == dt && classes[c].out == out)) ++c;
+        if (c == classes.size()) {
+            KClass kc;
+            kc.k = k; kc.dtype = dt; kc.out = out; kc.unit_off = 0; kc.units = 0; kc.blocks = 0;
+            classes.push_back(kc);
+            members.emplace_back();
+        }
+        members[c].push_back(i);
+        classes[c].units += (uint32_t)units_of(plans[i]);
+    }
+    {
+        std::vector<size_t> corder(classes.size());
+        std::iota(corder.begin(), corder.end(), 0);
+        std::stable_sort(corder.begin(), corder.end(),
+                         [&](size_t a, size_t b) { return classes[a].units > classes[b].units; });
+        std::vector<KClass> c2;
+        std::vector<std::vector<int>> m2;
+        for (size_t c : corder) { c2.push_back(classes[c]); m2.push_back(members[c]); }
+        classes.swap(c2);
+        members.swap(m2);
+    }
+    uint32_t off = 0;
+    for (size_t c = 0; c < classes.size(); ++c) {
+        classes[c].unit_off = off;
+        off += classes[c].units;
+        const int resident = fused_resident_blocks(classes[c].k, classes[c].dtype, classes[c].out);
+        classes[c].blocks = (uint32_t)std::min<uint64_t>((classes[c].units + 3) / 4, (uint64_t)resident);
+        std::stable_sort(members[c].begin(), members[c].end(),
+                         [&](int a, int b) { return units_of(plans[a]) > units_of(plans[b]); });
+    }
 
     BatchCtx *ctx = get_ctx(stream, ws);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -367,24 +433,30 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
     uint32_t *ubase = (uint32_t *)(h + L.off_base);
     uint32_t *umap = (uint32_t *)(h + L.off_umap);
     for (int i = 0; i < n; ++i) descs[i] = make_desc(&maps[i], &plans[i], (double *)((char *)ws + L.lut_off[i]));
-    uint32_t u = 0;
-    for (int oi = 0; oi < n; ++oi) {
-        const int i = order[oi];
-        ubase[i] = u;
-        const uint64_t cnt = units_of(plans[i]);
-        for (uint64_t k = 0; k < cnt; ++k) umap[u++] = (uint32_t)i;
+    for (size_t c = 0; c < classes.size(); ++c) {
+        uint32_t u = 0;  // unit numbers are local to the class
+        for (int i : members[c]) {
+            ubase[i] = u;
+            const uint64_t cnt = units_of(plans[i]);
+            for (uint64_t k = 0; k < cnt; ++k) umap[classes[c].unit_off + u++] = (uint32_t)i;
+        }
+    }
+    uint64_t sig = 1469598103934665603ull;  // FNV-1a over the class layout
+    for (const KClass &c : classes) {
+        const uint32_t f[6] = {(uint32_t)c.k, (uint32_t)c.dtype, (uint32_t)c.out, c.unit_off, c.units, c.blocks};
+        for (uint32_t v : f) { sig ^= v; sig *= 1099511628211ull; }
     }
 
-    const bool use_graph = (flags & CFAR_BATCH_GRAPH) && stream != nullptr;
+    const bool use_graph = (flags & CFAR_BATCH_GRAPH) && stream != nullptr && !g_timing.on;
     if (use_graph) {
         const bool match = sl.exec && sl.sig_head == L.head_bytes && sl.sig_units == total_units &&
-                           sl.sig_blocks == blocks && sl.sig_n == (uint32_t)n;
+                           sl.sig_layout == sig && sl.sig_n == (uint32_t)n;
         if (!match) {
             if (sl.exec) { (void)hipGraphExecDestroy(sl.exec); sl.exec = nullptr; }
             if (sl.graph) { (void)hipGraphDestroy(sl.graph); sl.graph = nullptr; }
             hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-            rc = enqueue_tiled_batch(sl, L, (char *)ws, (uint32_t)n, (uint32_t)total_units, stream);
+            rc = enqueue_tiled_batch(sl, L, (char *)ws, (uint32_t)n, classes, stream);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(stream, &g);
             if (rc != CFAR_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -394,13 +466,13 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
             sl.graph = g;
             sl.sig_head = L.head_bytes;
             sl.sig_units = (uint32_t)total_units;
-            sl.sig_blocks = blocks;
+            sl.sig_layout = sig;
             sl.sig_n = (uint32_t)n;
         }
         hipError_t e = hipGraphLaunch(sl.exec, stream);
         if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
     } else {
-        rc = enqueue_tiled_batch(sl, L, (char *)ws, (uint32_t)n, (uint32_t)total_units, stream);
+        rc = enqueue_tiled_batch(sl, L, (char *)ws, (uint32_t)n, classes, stream);
         if (rc != CFAR_OK) return rc;
     }
     hipError_t e = hipEventRecord(sl.done, stream);
@@ -415,23 +487,30 @@ static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, si
 {
     Plan p;
     if (!plan_geometry(m, cp.k_cols, cp.rows_per_unit, &p)) return set_error(CFAR_EINVAL, "no valid tile plan");
-    const size_t need = 256 + lut_bytes(m);
+    const size_t need = sizeof(BatchHeader) + lut_bytes(m);
     if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
     if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
     const uint64_t units = units_of(p);
     if (units >= (uint64_t)1 << 31) return set_error(CFAR_EINVAL, "map has too many work units");
-    uint32_t *counter = (uint32_t *)ws;
-    double *lut = (double *)((char *)ws + 256);
+    BatchHeader *hdr = (BatchHeader *)ws;
+    uint32_t *counter = hdr->counter;
+    double *lut = (double *)((char *)ws + sizeof(BatchHeader));
     FusedArgs a;
     std::memset(&a, 0, sizeof a);
     a.single = make_desc(m, &p, lut);
     a.counter = counter;
+    a.sink = hdr->sink;
     a.total_units = (uint32_t)units;
     a.n_maps = 1;
     hipError_t e = launch_lut(nullptr, a.single, 1, counter, stream);
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
-    e = launch_fused(a, stream);
+    e = timing_mark(g_timing.start, stream);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
+    e = launch_fused(a, p.k, m->dtype, has_outputs(m), stream);
     if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
+    e = timing_mark(g_timing.stop, stream);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
+    if (g_timing.on) g_timing.recorded = true;
     return CFAR_OK;
 }
 
@@ -636,6 +715,32 @@ int cfar_plan_load(const char *path)
     }
     std::lock_guard<std::mutex> lk(g_plan_mu);
     g_rules.swap(rules);
+    return CFAR_OK;
+}
+
+int cfar_timing_enable(int32_t on)
+{
+    if (on && !g_timing.start) {
+        hipError_t e = hipEventCreate(&g_timing.start);
+        if (e != hipSuccess) return hip_error(e, "hipEventCreate");
+        e = hipEventCreate(&g_timing.stop);
+        if (e != hipSuccess) return hip_error(e, "hipEventCreate");
+    }
+    g_timing.on = on != 0;
+    g_timing.recorded = false;
+    return CFAR_OK;
+}
+
+int cfar_timing_read(double *kernel_ms)
+{
+    if (!kernel_ms) return set_error(CFAR_EINVAL, "kernel_ms is NULL");
+    if (!g_timing.recorded) return set_error(CFAR_EINVAL, "no timed launch on this thread");
+    hipError_t e = hipEventSynchronize(g_timing.stop);
+    if (e != hipSuccess) return hip_error(e, "hipEventSynchronize(timing)");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, g_timing.start, g_timing.stop);
+    if (e != hipSuccess) return hip_error(e, "hipEventElapsedTime");
+    *kernel_ms = ms;
     return CFAR_OK;
 }
 

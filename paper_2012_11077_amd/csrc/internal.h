@@ -28,7 +28,7 @@ struct MapDesc {
     int32_t dtype;        // 0 = f32, 1 = f64
     int32_t k_cols;       // TILED: columns per lane (2, 4, 8)
     int32_t rs;           // TILED: output rows per work unit
-    int32_t halo_f;       // TILED: column halo, >= hf, multiple of 4
+    int32_t halo_f;       // TILED: column halo, >= hf + 1, multiple of 4
     int32_t tw;           // TILED: output columns per strip = 64*k_cols - 2*halo_f
     int32_t n_strips;     // TILED: strips across the columns
     int32_t n_rchunks;    // TILED: row chunks
@@ -45,6 +45,7 @@ struct FusedArgs {
     const uint32_t *unit_map;  // map index of every work unit (device), or nullptr
     const uint32_t *unit_base; // first work unit of every map (device), or nullptr
     uint32_t *counter;         // work counter (device), zeroed by the table kernel
+    uint32_t *sink;            // 512 bytes of device scratch: stores of lanes without outputs
     uint32_t total_units;
     uint32_t n_maps;
     MapDesc single;
@@ -54,12 +55,13 @@ struct FusedArgs {
 // (header + descriptors + unit tables) with one host-to-device copy; the
 // threshold tables that follow are filled on the device.
 struct BatchHeader {
-    uint32_t counter;
+    uint32_t counter[16];  // one work counter per kernel class (k, dtype, outputs)
     uint32_t n_maps;
     uint32_t total_units;
-    uint32_t pad[61];
+    uint32_t pad[46];
+    uint32_t sink[128];    // stores of lanes without outputs land here
 };
-static_assert(sizeof(BatchHeader) == 256, "BatchHeader must stay 256 bytes");
+static_assert(sizeof(BatchHeader) == 768, "BatchHeader must stay 768 bytes");
 
 // SAT tile geometry of the PLAIN form: 32 rows x 256 columns per workgroup.
 constexpr int kSatTH = 32;
@@ -102,11 +104,13 @@ hipError_t launch_lut(const MapDesc *descs, const MapDesc &single, int n, uint32
 // Eight-corner stencil over the PLAIN FP64 SAT of one map.
 hipError_t launch_stencil_plain(const MapDesc &d, const double *sat, hipStream_t stream);
 
-// Persistent TILED kernel over all work units in `args`.
-hipError_t launch_fused(const FusedArgs &args, hipStream_t stream);
+// Persistent TILED kernel (columns per lane k, map dtype, out = maps may
+// carry the optional training-sum / threshold outputs) over all work units
+// in `args`; every map in `args` must belong to that class.
+hipError_t launch_fused(const FusedArgs &args, int k, int dtype, bool out, hipStream_t stream);
 
-// Number of persistent workgroups of the TILED kernel that fit the device.
-int fused_resident_blocks();
+// Number of persistent workgroups of that kernel that fit the device.
+int fused_resident_blocks(int k, int dtype, bool out);
 
 constexpr int kFusedThreads = 256;  // 4 independent waves per workgroup
 constexpr int kMaxK = 8;

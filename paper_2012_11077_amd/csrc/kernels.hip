@@ -12,7 +12,7 @@
 //       eight corners of eq. (4) read from the FP64 integral image.
 //   lut_kernel
 //       per-map table beta(n) = alpha(n)/n = expm1(-ln(Pfa)/n) for clipped
-//       border windows; also zeroes the work counter of the fused kernel.
+//       border windows; also zeroes the work counters of the fused kernels.
 //   fused_kernel
 //       TILED form: persistent, one wave per work unit (a strip of 64*K
 //       columns x rs rows of one map).  The eight corners of eq. (4) are taken
@@ -255,7 +255,7 @@ hipError_t launch_sat2d(const void *x, int dtype, int64_t rows, int64_t cols, in
 __global__ void __launch_bounds__(256) lut_kernel(const MapDesc *__restrict__ descs, MapDesc single,
                                                   uint32_t *counter)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && counter) *counter = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 16 && counter) counter[threadIdx.x] = 0u;
     const MapDesc *d = descs ? descs + blockIdx.x : &single;
     double *lut = d->lut;
     const double nl = d->neg_log_pfa;
@@ -320,118 +320,183 @@ hipError_t launch_stencil_plain(const MapDesc &d, const double *sat, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// TILED form: persistent fused kernel.
+// TILED form: persistent fused kernel, one instantiation per (K, T).
+//
+// One wave owns a work unit: a strip of W = 64*K map columns (the strip's
+// output columns plus a halo of H >= hf + 1 columns on each side; lane l
+// holds columns l*K .. l*K+K-1 of the strip) and rs output rows.  Per output
+// row r:
+//   1. four FP64 running column sums of the strip, started at row ra - hr,
+//      advanced to rows r+hr, r+gr, r-gr-1, r-hr-1 (lead/lag accumulators
+//      that add the same rows in the same order, so each lag equals the lead
+//      of an earlier step): their differences are the column sums of the
+//      outer and inner windows, i.e. the row corners of eq. (4);
+//   2. an FP64 row prefix of those column sums across the strip (in-lane
+//      serial over K columns, then a DPP scan over the 64 lanes);
+//   3. the column corners of eq. (4): prefix differences at p + h and
+//      p - h - 1, read back from LDS;
+//   4. training sum, N, T = beta(N) * sum, decision, mask store.
+// The next row's loads are issued before the current row is processed.
 // ---------------------------------------------------------------------------
 
-// Per-wave LDS: two prefix rows (outer, inner) of 64*K + 1 doubles each; the
-// first entry of each row is a zero so that an empty prefix needs no branch.
-constexpr int kQStride = 64 * kMaxK + 8;
+// Global-memory pointers (address space 1): descriptors hand the kernels
+// generic pointers, which would otherwise compile to flat accesses.
+#define CFAR_GLOBAL __attribute__((address_space(1)))
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ const CFAR_GLOBAL T *gbl(const T *p) { return (const CFAR_GLOBAL T *)p; }
+template <typename T>
+__device__ __forceinline__ CFAR_GLOBAL T *gbl_w(T *p) { return (CFAR_GLOBAL T *)p; }
 
-// Load K consecutive values of one row starting at column c (zero outside [0, F)).
-template <int K, typename T>
-__device__ __forceinline__ void load_k(const T *__restrict__ row, int c, int F, bool full, bool vec, double (&v)[K])
+// Loads of K consecutive values of one row (row: wave-uniform byte pointer)
+// starting at strip column c.  FAST: the K columns lie inside the map and the
+// access is 16-byte aligned (vector loads).  !FAST: each column is clamped
+// into [0, F) and the value zeroed outside, so every access stays in bounds.
+template <int K, typename T, bool FAST>
+__device__ __forceinline__ void ldk(const CFAR_GLOBAL char *row, int c, int F, T (&v)[K])
 {
-    if (full) {
+    if constexpr (FAST) {
+        const uint32_t off = (uint32_t)c * (uint32_t)sizeof(T);
         if constexpr (sizeof(T) == 4) {
-            if (vec && (K % 4) == 0) {
+            if constexpr (K == 2) {
+                const f32x2 f = *(const CFAR_GLOBAL f32x2 *)(row + off);
+                v[0] = f.x; v[1] = f.y;
+            } else {
 #pragma unroll
                 for (int q = 0; q < K / 4; ++q) {
-                    const float4 f = *((const float4 *)(row + c) + q);
+                    const f32x4 f = *(const CFAR_GLOBAL f32x4 *)(row + off + 16u * q);
                     v[4 * q + 0] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
                 }
-                return;
-            }
-            if (vec && K == 2) {
-                const float2 f = *((const float2 *)(row + c));
-                v[0] = f.x; v[1] = f.y;
-                return;
             }
         } else {
-            if (vec && (K % 2) == 0) {
 #pragma unroll
-                for (int q = 0; q < K / 2; ++q) {
-                    const double2 f = *((const double2 *)(row + c) + q);
-                    v[2 * q + 0] = f.x; v[2 * q + 1] = f.y;
-                }
-                return;
+            for (int q = 0; q < K / 2; ++q) {
+                const f64x2 f = *(const CFAR_GLOBAL f64x2 *)(row + off + 16u * q);
+                v[2 * q + 0] = f.x; v[2 * q + 1] = f.y;
             }
         }
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] = (double)row[c + k];
     } else {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int cc = c + k;
-            v[k] = (cc >= 0 && cc < F) ? (double)row[cc] : 0.0;
+            const int cl = min(max(cc, 0), F - 1);
+            const T t = *(const CFAR_GLOBAL T *)(row + (uint32_t)cl * (uint32_t)sizeof(T));
+            v[k] = (cc >= 0 && cc < F) ? t : T(0);
         }
     }
 }
 
-template <int K>
-__device__ __forceinline__ void acc_k(double (&a)[K], const double (&v)[K])
+// acc += s * v with s = 1.0 (row inside the map) or 0.0 (outside): a
+// branch-free add that is bit-identical to adding or skipping the row.
+template <int K, typename T>
+__device__ __forceinline__ void acc_row(double (&a)[K], const T (&v)[K], double s)
 {
 #pragma unroll
-    for (int k = 0; k < K; ++k) a[k] += v[k];
+    for (int k = 0; k < K; ++k) a[k] = __builtin_fma(s, (double)v[k], a[k]);
 }
 
-template <int K, typename T>
+// Lane-major LDS layout of one prefix row: position p = l*K + k at
+// [k*64 + l].  Rows K .. 2K-2 repeat rows 0 .. K-2 shifted down one lane
+// ([(K+k)*64 + l] holds element k of lane l+1).  Reading position p + o for
+// element k of every lane, with o = q*K + s (0 <= s < K), is then one load
+// at [(k+s)*64 + l+q] for every k: no per-element address select.  Lane
+// indices wrap inside the row so every address stays in the wave's region
+// (wrapped values only reach positions that are not outputs).
+template <int K>
+struct OffsetRead {
+    int base;
+    __device__ __forceinline__ void init(int o, int lane)
+    {
+        const int q = o >= 0 ? o / K : -((-o + K - 1) / K);
+        const int s = o - q * K;
+        base = s * 64 + ((lane + q) & 63);
+    }
+    __device__ __forceinline__ double get(const double *__restrict__ q, int k) const { return q[base + k * 64]; }
+};
+constexpr int q_rows(int K) { return 2 * K - 1; }
+
+// FAST: every lane's K columns lie inside the map, the map and mask rows are
+// aligned for vector access, the strip's output columns are at least hf away
+// from both map borders (so only rows can be clipped), and lanes hold either
+// K output columns or none.  Otherwise the general path.
+//
+// Interior rows of FAST units run in a straight-line loop (no branches, no
+// optional stores) with the next row's loads in flight, so the compiler's
+// memory waits stay exact; border rows and general units run a plain loop.
+template <int K, typename T, bool FAST, bool OUT>
 __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, double *__restrict__ qo,
-                           double *__restrict__ qi, int lane)
+                           double *__restrict__ qi, int lane, uint32_t *__restrict__ sink)
 {
-    constexpr int W = 64 * K;
     const int R = d.rows, F = d.cols;
     const int hr = d.hr, hf = d.hf, gr = d.gr, gf = d.gf;
     const int H = d.halo_f;
     const int c_out0 = strip * d.tw;
     const int c_out1 = min(c_out0 + d.tw, F);
-    const int cs = c_out0 - H;  // map column of position 0 of this strip
+    const int cs = c_out0 - H;  // map column of strip position 0
     const int ra = rchunk * d.rs;
     const int rb = min(ra + d.rs, R);
     const int c_lane = cs + lane * K;
-    const bool full = c_lane >= 0 && c_lane + K <= F;
-    const bool vec = (d.vec_ok & 1) != 0;
     const T *__restrict__ X = (const T *)d.x;
     const int64_t ld = d.ld;
-    const int lo_row = max(0, ra - hr);  // first row any accumulator may add
+    const int lo_row = max(0, ra - hr);  // first row any accumulator adds
 
-    // lane's output positions: p = lane*K + k, column j = cs + p, output iff c_out0 <= j < c_out1
     const bool lane_any_out = (c_lane + K > c_out0) && (c_lane < c_out1);
-    const bool lane_all_out = (c_lane >= c_out0) && (c_lane + K <= c_out1);
     const bool lane_col_interior = (c_lane >= hf) && (c_lane + K - 1 + hf < F);
-    const double beta_full = d.lut[d.n_full];
+    const double beta_full = gbl(d.lut)[d.n_full];
 
-    if (lane == 0) { qo[0] = 0.0; qi[0] = 0.0; }
+    OffsetRead<K> rd_oh, rd_ol, rd_ih, rd_il;
+    rd_oh.init(hf, lane);
+    rd_ol.init(-hf - 1, lane);
+    rd_ih.init(gf, lane);
+    rd_il.init(-gf - 1, lane);
 
-    // Column prefix sums C(i) = sum of X over rows [ra - hr, i] of each lane column.
-    double Cl[K], Cg1[K], Cg0[K], Ch0[K], v[K];
+    auto rowp = [&](int i) -> const CFAR_GLOBAL char * {
+        const int ic = min(max(i, 0), R - 1);
+        return (const CFAR_GLOBAL char *)gbl(X + (int64_t)ic * ld);
+    };
+
+    double Cl[K], Cg1[K], Cg0[K], Ch0[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) { Cl[k] = 0.0; Cg1[k] = 0.0; Cg0[k] = 0.0; Ch0[k] = 0.0; }
 
-    // Warm-up: C up to row ra + hr - 1, snapshots at ra - gr - 2 and ra + gr - 1.
-    for (int i = ra - hr; i < ra + hr; ++i) {
-        if (i >= 0 && i < R) {
-            load_k<K, T>(X + (int64_t)i * ld, c_lane, F, full, vec, v);
-            acc_k<K>(Cl, v);
-        }
-        if (i == ra - gr - 2) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) Cg0[k] = Cl[k];
-        }
-        if (i == ra + gr - 1) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) Cg1[k] = Cl[k];
-        }
+    // Warm-up: C over rows [ra - hr, ra + hr - 1], snapshots at ra-gr-2 and
+    // ra+gr-1; four rows' loads in flight at a time.
+    const int e = ra + hr;
+    for (int i0 = ra - hr; i0 < e; i0 += 4) {
+        T w0[K], w1[K], w2[K], w3[K];
+        ldk<K, T, FAST>(rowp(i0 + 0), c_lane, F, w0);
+        ldk<K, T, FAST>(rowp(i0 + 1), c_lane, F, w1);
+        ldk<K, T, FAST>(rowp(i0 + 2), c_lane, F, w2);
+        ldk<K, T, FAST>(rowp(i0 + 3), c_lane, F, w3);
+#define CFAR_WARM(J, WV)                                                                    \
+    {                                                                                       \
+        const int i = i0 + J;                                                               \
+        acc_row<K, T>(Cl, WV, (i >= 0 && i < R && i < e) ? 1.0 : 0.0);                    \
+        if (i == ra - gr - 2) {                                                             \
+            _Pragma("unroll") for (int k = 0; k < K; ++k) Cg0[k] = Cl[k];                   \
+        }                                                                                   \
+        if (i == ra + gr - 1) {                                                             \
+            _Pragma("unroll") for (int k = 0; k < K; ++k) Cg1[k] = Cl[k];                   \
+        }                                                                                   \
+    }
+        CFAR_WARM(0, w0)
+        CFAR_WARM(1, w1)
+        CFAR_WARM(2, w2)
+        CFAR_WARM(3, w3)
+#undef CFAR_WARM
     }
 
-    const bool vec_mask = ((d.vec_ok & 2) != 0) && lane_all_out;
-    for (int r = ra; r < rb; ++r) {
-        // advance the four accumulators to C(r+hr), C(r+gr), C(r-gr-1), C(r-hr-1)
-        if (r + hr < R) { load_k<K, T>(X + (int64_t)(r + hr) * ld, c_lane, F, full, vec, v); acc_k<K>(Cl, v); }
-        if (r + gr < R) { load_k<K, T>(X + (int64_t)(r + gr) * ld, c_lane, F, full, vec, v); acc_k<K>(Cg1, v); }
-        if (r - gr - 1 >= lo_row) { load_k<K, T>(X + (int64_t)(r - gr - 1) * ld, c_lane, F, full, vec, v); acc_k<K>(Cg0, v); }
-        if (r - hr - 1 >= lo_row) { load_k<K, T>(X + (int64_t)(r - hr - 1) * ld, c_lane, F, full, vec, v); acc_k<K>(Ch0, v); }
-
-        // column window sums (row corners of eq. 4) and their row prefix within the lane
+    const int lane_dn = (lane + 63) & 63;
+    // Advance the column prefix sums to rows r+hr, r+gr, r-gr-1, r-hr-1; form
+    // the column window sums (row corners of eq. 4); prefix them across the
+    // strip and publish the prefixes in LDS.
+    auto accumulate = [&](int r, const T(&b)[5][K]) {
+        acc_row<K, T>(Cl, b[0], r + hr < R ? 1.0 : 0.0);
+        acc_row<K, T>(Cg1, b[1], r + gr < R ? 1.0 : 0.0);
+        acc_row<K, T>(Cg0, b[2], r - gr - 1 >= lo_row ? 1.0 : 0.0);
+        acc_row<K, T>(Ch0, b[3], r - hr - 1 >= lo_row ? 1.0 : 0.0);
         double po[K], pi[K];
         po[0] = Cl[0] - Ch0[0];
         pi[0] = Cg1[0] - Cg0[0];
@@ -440,145 +505,246 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, double *__re
             po[k] = po[k - 1] + (Cl[k] - Ch0[k]);
             pi[k] = pi[k - 1] + (Cg1[k] - Cg0[k]);
         }
-        // wave-wide exclusive offsets
         const double eo = wave_shift_up1(wave_incl_scan(po[K - 1]));
         const double ei = wave_shift_up1(wave_incl_scan(pi[K - 1]));
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            qo[1 + lane * K + k] = eo + po[k];
-            qi[1 + lane * K + k] = ei + pi[k];
+            const double vo = eo + po[k], vi = ei + pi[k];
+            qo[k * 64 + lane] = vo;
+            qi[k * 64 + lane] = vi;
+            if (k < K - 1) {
+                qo[(K + k) * 64 + lane_dn] = vo;
+                qi[(K + k) * 64 + lane_dn] = vi;
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-        if (lane_any_out) {
-            // column corners of eq. (4) from the row prefixes: box = Q(p+h) - Q(p-h-1)
-            const bool row_interior = (r >= hr) && (r + hr < R);
-            const bool interior = row_interior && lane_col_interior;
-            const int nro = clip_len(r, hr, R), nri = clip_len(r, gr, R);
-            double cut[K];
-            load_k<K, T>(X + (int64_t)r * ld, c_lane, F, full, vec, cut);
-            uint8_t m[K];
-            const int64_t orow = (int64_t)r * d.ld_mask;
+    };
+    auto train_sum_at = [&](int k) -> double {
+        // column corners of eq. (4): box = Q(p + h) - Q(p - h - 1), outer minus inner
+        return (rd_oh.get(qo, k) - rd_ol.get(qo, k)) - (rd_ih.get(qi, k) - rd_il.get(qi, k));
+    };
+    CFAR_GLOBAL uint8_t *sink_b = (CFAR_GLOBAL uint8_t *)gbl_w(sink + lane * 2);
+    // Interior row of a FAST unit: N = n_full, beta = beta_full, every lane
+    // computes; lanes without outputs store into the sink.
+    auto output_fast = [&](int r, const T(&xcut)[K]) {
+        uint32_t bits[(K + 3) / 4];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                // positions outside this strip's outputs are evaluated at a clamped
-                // position (their results are discarded) so every index stays in bounds
-                const int p = min(max(lane * K + k, H), W - H - 1);
-                const double bo = qo[p + hf + 1] - qo[p - hf];
-                const double bi = qi[p + gf + 1] - qi[p - gf];
-                const double st = bo - bi;
-                int nt;
-                double beta;
-                if (interior) {
-                    nt = d.n_full;
-                    beta = beta_full;
-                } else {
-                    const int j = min(cs + p, F - 1);
-                    nt = nro * clip_len(j, hf, F) - nri * clip_len(j, gf, F);
-                    beta = d.lut[nt];
-                }
-                const double thr = beta * st;
-                m[k] = (uint8_t)(nt > 0 && cut[k] > thr);
-                if (d.train_sum || d.thresh) {
-                    const int j = c_lane + k;
-                    if (j >= c_out0 && j < c_out1) {
-                        if (d.train_sum) d.train_sum[orow + j] = st;
-                        if (d.thresh) d.thresh[orow + j] = nt > 0 ? thr : INFINITY;
-                    }
-                }
-            }
-            uint8_t *mrow = d.mask + orow;
-            if (vec_mask && (K % 4) == 0) {
+        for (int q = 0; q < (K + 3) / 4; ++q) bits[q] = 0u;
 #pragma unroll
-                for (int q = 0; q < K / 4; ++q) {
-                    const uint32_t w = (uint32_t)m[4 * q] | ((uint32_t)m[4 * q + 1] << 8) |
-                                       ((uint32_t)m[4 * q + 2] << 16) | ((uint32_t)m[4 * q + 3] << 24);
-                    __builtin_nontemporal_store(w, (uint32_t *)(mrow + c_lane) + q);
-                }
-            } else if (vec_mask && K == 2) {
-                const uint16_t w = (uint16_t)((uint32_t)m[0] | ((uint32_t)m[1] << 8));
-                __builtin_nontemporal_store(w, (uint16_t *)(mrow + c_lane));
-            } else {
+        for (int k = 0; k < K; ++k) {
+            const double thr = beta_full * train_sum_at(k);
+            bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
+        }
+        CFAR_GLOBAL uint8_t *mdst = gbl_w(d.mask) + (int64_t)r * d.ld_mask + c_lane;
+        CFAR_GLOBAL uint8_t *dst = lane_any_out ? mdst : sink_b;
+        if constexpr (K == 2) {
+            __builtin_nontemporal_store((uint16_t)bits[0], (CFAR_GLOBAL uint16_t *)dst);
+        } else {
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int j = c_lane + k;
-                    if (j >= c_out0 && j < c_out1) mrow[j] = m[k];
+            for (int q = 0; q < K / 4; ++q) __builtin_nontemporal_store(bits[q], (CFAR_GLOBAL uint32_t *)dst + q);
+        }
+    };
+    // Any row: N and beta per cell.  Branch-free: every cell is computed and
+    // its byte stored either into the mask or, outside this strip's outputs,
+    // into the sink.  The per-cell table loads are issued by prep() before the
+    // next row's loads, so waiting for them never waits for the prefetch.
+    struct Prep {
+        int nt[K];
+        double beta[K];
+    };
+    auto prep = [&](int r, Prep &pp) {
+        const int nro = clip_len(r, hr, R), nri = clip_len(r, gr, R);
+        const bool interior = (r >= hr) && (r + hr < R) && lane_col_interior;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int jc = min(max(c_lane + k, 0), F - 1);
+            pp.nt[k] = interior ? d.n_full : nro * clip_len(jc, hf, F) - nri * clip_len(jc, gf, F);
+            pp.beta[k] = gbl(d.lut)[pp.nt[k]];
+        }
+    };
+    auto output_general = [&](int r, const T(&xcut)[K], const Prep &pp) {
+        const int64_t orow = (int64_t)r * d.ld_mask;
+        CFAR_GLOBAL uint8_t *mrow = gbl_w(d.mask) + orow;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double st = train_sum_at(k);
+            const int j = c_lane + k;
+            const double thr = pp.beta[k] * st;
+            const bool own = j >= c_out0 && j < c_out1;
+            CFAR_GLOBAL uint8_t *dst = own ? mrow + j : sink_b + k;
+            *dst = (uint8_t)(pp.nt[k] > 0 && (double)xcut[k] > thr);
+            if constexpr (OUT) {
+                if (own) {
+                    if (d.train_sum) gbl_w(d.train_sum)[orow + j] = st;
+                    if (d.thresh) gbl_w(d.thresh)[orow + j] = pp.nt[k] > 0 ? thr : INFINITY;
                 }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+    };
+    auto issue = [&](int r, T(&b)[5][K]) {
+        ldk<K, T, FAST>(rowp(r + hr), c_lane, F, b[0]);
+        ldk<K, T, FAST>(rowp(r + gr), c_lane, F, b[1]);
+        ldk<K, T, FAST>(rowp(r - gr - 1), c_lane, F, b[2]);
+        ldk<K, T, FAST>(rowp(r - hr - 1), c_lane, F, b[3]);
+        ldk<K, T, FAST>(rowp(r), c_lane, F, b[4]);
+    };
+    auto general_rows = [&](int r0, int r1) {
+        for (int r = r0; r < r1; ++r) {
+            T b[5][K];
+            Prep pp;
+            prep(r, pp);
+            issue(r, b);
+            accumulate(r, b);
+            output_general(r, b[4], pp);
+            __builtin_amdgcn_wave_barrier();
+        }
+    };
+    // Rows with the next row's loads in flight (two alternating buffers).
+    // FAST units without the optional outputs take the straight-line output
+    // on interior rows; all other rows take the general output.
+    auto pipelined_fast = [&](int r0, int r1) {
+        if (r0 >= r1) return;
+        T A[5][K], B[5][K];
+        issue(r0, A);
+        int r = r0;
+        for (; r + 1 < r1; r += 2) {
+            issue(r + 1, B);  // rows are clamped, so issuing past the end is harmless
+            accumulate(r, A);
+            output_fast(r, A[4]);
+            issue(r + 2, A);
+            accumulate(r + 1, B);
+            output_fast(r + 1, B[4]);
+        }
+        if (r < r1) {
+            accumulate(r, A);
+            output_fast(r, A[4]);
+        }
+    };
+    auto pipelined_general = [&](int r0, int r1) {
+        if (r0 >= r1) return;
+        T A[5][K], B[5][K];
+        Prep PA, PB;
+        issue(r0, A);
+        int r = r0;
+        for (; r + 1 < r1; r += 2) {
+            prep(r, PA);
+            issue(r + 1, B);
+            accumulate(r, A);
+            output_general(r, A[4], PA);
+            prep(r + 1, PB);
+            issue(r + 2, A);
+            accumulate(r + 1, B);
+            output_general(r + 1, B[4], PB);
+        }
+        if (r < r1) {
+            prep(r, PA);
+            accumulate(r, A);
+            output_general(r, A[4], PA);
+        }
+    };
+    if (FAST && !OUT) {
+        const int r_in0 = min(max(hr, ra), rb);
+        const int r_in1 = max(min(R - hr, rb), r_in0);
+        general_rows(ra, r_in0);
+        pipelined_fast(r_in0, r_in1);
+        general_rows(r_in1, rb);
+    } else {
+        pipelined_general(ra, rb);
     }
 }
 
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+
+
+template <int K, typename T, bool OUT>
 __global__ void __launch_bounds__(kFusedThreads) fused_kernel(FusedArgs args)
 {
-    __shared__ double qbuf[kFusedThreads / 64][2][kQStride];
+    __shared__ double qbuf[kFusedThreads / 64][2][q_rows(K) * 64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     double *qo = qbuf[wave][0];
     double *qi = qbuf[wave][1];
     for (;;) {
         uint32_t u = 0;
-        if (lane == 0) u = atomicAdd(args.counter, 1u);
+        if (lane == 0) u = __hip_atomic_fetch_add(args.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         u = wave_uniform(u);
         if (u >= args.total_units) break;
-        const MapDesc *dp;
-        uint32_t local;
+        // descriptor and unit tables are wave-uniform: global (scalar) loads
+        uint32_t local = u;
+        MapDesc d;
         if (args.descs) {
-            const uint32_t m = wave_uniform(args.unit_map[u]);
-            dp = args.descs + m;
-            local = u - wave_uniform(args.unit_base[m]);
+            const uint32_t m = wave_uniform(gbl(args.unit_map)[u]);
+            local = u - wave_uniform(gbl(args.unit_base)[m]);
+            const CFAR_GLOBAL uint32_t *src = (const CFAR_GLOBAL uint32_t *)gbl(args.descs + m);
+            uint32_t w[sizeof(MapDesc) / 4];
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(MapDesc) / 4); ++i) w[i] = src[i];
+            __builtin_memcpy(&d, w, sizeof(MapDesc));
         } else {
-            dp = &args.single;
-            local = u;
+            d = args.single;
         }
-        const MapDesc d = *dp;
         const int strip = (int)(local % (uint32_t)d.n_strips);
         const int rchunk = (int)(local / (uint32_t)d.n_strips);
-        const int key = d.k_cols * 2 + d.dtype;
-        switch (key) {
-        case 2 * 2 + 0: fused_unit<2, float>(d, strip, rchunk, qo, qi, lane); break;
-        case 2 * 2 + 1: fused_unit<2, double>(d, strip, rchunk, qo, qi, lane); break;
-        case 4 * 2 + 0: fused_unit<4, float>(d, strip, rchunk, qo, qi, lane); break;
-        case 4 * 2 + 1: fused_unit<4, double>(d, strip, rchunk, qo, qi, lane); break;
-        case 8 * 2 + 0: fused_unit<8, float>(d, strip, rchunk, qo, qi, lane); break;
-        case 8 * 2 + 1: fused_unit<8, double>(d, strip, rchunk, qo, qi, lane); break;
-        default: break;
-        }
+        const int cs = strip * d.tw - d.halo_f;
+        const bool fast = d.vec_ok == 3 && cs >= 0 && cs + 64 * K <= d.cols && (d.halo_f % K) == 0;
+        if (fast)
+            fused_unit<K, T, true, OUT>(d, strip, rchunk, qo, qi, lane, args.sink);
+        else
+            fused_unit<K, T, false, OUT>(d, strip, rchunk, qo, qi, lane, args.sink);
     }
 }
 
-hipError_t launch_fused(const FusedArgs &args, hipStream_t stream)
+#define CFAR_FUSED_VARIANTS(X_)                                                                          \
+    X_(2, float, false) X_(4, float, false) X_(8, float, false) X_(2, double, false) X_(4, double, false) \
+    X_(8, double, false) X_(2, float, true) X_(4, float, true) X_(8, float, true) X_(2, double, true)     \
+    X_(4, double, true) X_(8, double, true)
+
+static const void *fused_fn(int k, int dtype, bool out)
 {
-    const int resident = fused_resident_blocks();
-    const uint32_t waves_needed = args.total_units;
-    uint32_t blocks = (waves_needed + (kFusedThreads / 64) - 1) / (kFusedThreads / 64);
-    if (blocks > (uint32_t)resident) blocks = (uint32_t)resident;
-    if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(fused_kernel, dim3(blocks), dim3(kFusedThreads), 0, stream, args);
-    return hipGetLastError();
+#define CFAR_PICK(K_, T_, O_) \
+    if (k == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) return (const void *)fused_kernel<K_, T_, O_>;
+    CFAR_FUSED_VARIANTS(CFAR_PICK)
+#undef CFAR_PICK
+    return nullptr;
 }
 
-int fused_resident_blocks()
+int fused_resident_blocks(int k, int dtype, bool out)
 {
-    static int cached[64] = {0};
+    static int cached[64][16] = {{0}};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-    if (cached[dev] > 0) return cached[dev];
+    const int slot = ((k == 2 ? 0 : k == 4 ? 1 : 2) * 2 + dtype) * 2 + (out ? 1 : 0);
+    if (cached[dev][slot] > 0) return cached[dev][slot];
+    const void *fn = fused_fn(k, dtype, out);
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_kernel, kFusedThreads, 0) != hipSuccess ||
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFusedThreads, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     if (cus < 1) cus = 1;
-    cached[dev] = per_cu * cus;
-    return cached[dev];
+    cached[dev][slot] = per_cu * cus;
+    return cached[dev][slot];
+}
+
+hipError_t launch_fused(const FusedArgs &args, int k, int dtype, bool out, hipStream_t stream)
+{
+    const int resident = fused_resident_blocks(k, dtype, out);
+    uint32_t blocks = (args.total_units + (kFusedThreads / 64) - 1) / (kFusedThreads / 64);
+    if (blocks > (uint32_t)resident) blocks = (uint32_t)resident;
+    if (blocks == 0) blocks = 1;
+#define CFAR_LAUNCH(K_, T_, O_)                                                                              \
+    if (k == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) {                                        \
+        hipLaunchKernelGGL((fused_kernel<K_, T_, O_>), dim3(blocks), dim3(kFusedThreads), 0, stream, args); \
+        return hipGetLastError();                                                                            \
+    }
+    CFAR_FUSED_VARIANTS(CFAR_LAUNCH)
+#undef CFAR_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 }  // namespace cfar

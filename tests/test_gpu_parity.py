@@ -65,8 +65,8 @@ EDGE = [
     (700, 5, 1, 1, 6, 0, 1e-3),        # no training along columns
     (97, 131, 0, 0, 5, 5, 1e-4),       # no guard
     (64, 400, 4, 4, 24, 24, 1e-5),
-    (40, 1100, 2, 10, 3, 240, 1e-4),   # column half-width near the TILED limit
-    (130, 520, 1, 0, 2, 250, 1e-3),    # hf = 250
+    (40, 1100, 2, 10, 3, 237, 1e-4),   # column half-width at the TILED limit (247)
+    (130, 520, 1, 0, 2, 247, 1e-3),    # hf = 247
     (256, 456, 4, 4, 24, 24, 1e-5),    # exactly one strip wide at k = 8
     (513, 457, 3, 3, 16, 16, 1e-6),    # ragged tails
 ]
