@@ -62,6 +62,48 @@ def measured_traffic():
     return t
 
 
+def _counter_per_dispatch(path, counter, kernel_substr, reduce="mean"):
+    """Mean (or max) value of a rocprofv3 counter per dispatch of the kernels
+    whose name contains kernel_substr, from the sqlite database(s) under path."""
+    import glob
+    import sqlite3
+    vals = {}
+    for db in glob.glob(os.path.join(path, "**", "*.db"), recursive=True):
+        c = sqlite3.connect(db)
+        for name, disp, v in c.execute("select kernel_name, dispatch_id, value from counters_collection "
+                                       "where counter_name = ?", (counter,)):
+            if kernel_substr in name:
+                vals[(db, disp)] = vals.get((db, disp), 0.0) + float(v)
+        c.close()
+    if not vals:
+        raise SystemExit("no %s samples for %r under %s" % (counter, kernel_substr, path))
+    if reduce == "max":
+        return max(vals.values()), len(vals)
+    return sum(vals.values()) / len(vals), len(vals)
+
+
+def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, command):
+    """HBM bytes per launch of the fused kernel from two rocprofv3 counter runs
+    (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for the 1 GiB device copy of --copy-probe; written to
+    the traffic file with the kernel source hash."""
+    copy_bytes = float(1 << 30)
+    # the probe's copies are its largest dispatches (the fill before them reads nothing)
+    cf, _ = _counter_per_dispatch(copy_fetch_dir, "FETCH_SIZE", "", reduce="max")
+    cw, _ = _counter_per_dispatch(copy_write_dir, "WRITE_SIZE", "", reduce="max")
+    f_scale, w_scale = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    fk, n1 = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", "fused_kernel")
+    wk, n2 = _counter_per_dispatch(write_dir, "WRITE_SIZE", "fused_kernel")
+    t = {"kernel": "fused_kernel", "workload": workload, "kernel_sha": kernel_source_sha(),
+         "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
+         "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+         "bytes_per_launch": int(fk * 1024.0 * f_scale + wk * 1024.0 * w_scale),
+         "dispatches": [n1, n2], "command": command}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(t, f, indent=1)
+    print(json.dumps(t), flush=True)
+
+
 def percentile(v, q):
     v = sorted(v)
     if not v:
@@ -87,6 +129,109 @@ def cpu_baseline(specs, arrays, budget_s=12.0):
     return {"value": cells / t_tot, "unit": "cells/s", "cores": 1, "kind": "oracle",
             "sample": "first %d of %d maps of the workload (%d cells), oracle FP64 single thread, %.1f s"
                       % (n, len(specs), cells, t_tot)}
+
+
+def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
+    """The serving workload: n_streams simulated drone streams, each emitting
+    frames of its own fixed size at Poisson rate 50 Hz, submitted from pinned
+    host memory to the library's server (continuous batching over 4 HIP
+    streams, admission by device memory); latency is frame arrival (its
+    scheduled Poisson time) to the mask back in host memory."""
+    import threading
+    import torch
+    from paper_2012_11077_amd import cfar2d as C
+    from paper_2012_11077_amd import synth
+    streams = synth.config4_streams(n_streams, seed)
+    rng = np.random.default_rng(seed)
+    frames_per_stream, masks_per_stream = 4, 16
+    frames, free_masks = [], []
+    for st in streams:
+        fr = []
+        for j in range(frames_per_stream):
+            sp = synth.stream_frame_spec(st, j)
+            fr.append((torch.from_numpy(synth.generate(sp)).pin_memory(), sp.window, sp.cells))
+        frames.append(fr)
+        free_masks.append([torch.empty((st["rows"], st["cols"]), dtype=torch.uint8).pin_memory()
+                           for _ in range(masks_per_stream)])
+    # merged Poisson arrival schedule
+    arrivals = []
+    for k, st in enumerate(streams):
+        t = 0.0
+        while True:
+            t += rng.exponential(1.0 / st["rate_hz"])
+            if t >= seconds:
+                break
+            arrivals.append((t, k))
+    arrivals.sort()
+    srv = C.Server(device_budget_bytes=4 << 30, max_inflight_frames=96, n_hip_streams=4, queue_depth=512,
+                   max_batch_frames=32)
+    lock = threading.Lock()
+    pending = {}            # ticket -> (arrival_ns, stream, mask, cells)
+    lat_ms, done_cells = [], [0]
+    stop = [False]
+
+    def poller():
+        while True:
+            cs = srv.poll(256, 20000)
+            with lock:
+                for c in cs:
+                    arr, k, m, cells = pending.pop(c.ticket)
+                    if c.status == C.CFAR_OK:
+                        lat_ms.append((c.t_done_ns - arr) / 1e6)
+                        done_cells[0] += cells
+                    free_masks[k].append(m)
+                if stop[0] and not pending:
+                    return
+
+    th = threading.Thread(target=poller, daemon=True)
+    th.start()
+    t0 = time.monotonic_ns()
+    eagain = waited = 0
+    next_log = log_every
+    fi = [0] * len(streams)
+    for (ta, k) in arrivals:
+        arr_ns = t0 + int(ta * 1e9)
+        now = time.monotonic_ns()
+        if arr_ns > now:
+            time.sleep((arr_ns - now) / 1e9)
+        if ta >= next_log:
+            log("serving: %.0f s, %d frames done" % (ta, len(lat_ms)))
+            next_log += log_every
+        x, win, cells = frames[k][fi[k] % frames_per_stream]
+        fi[k] += 1
+        while True:
+            with lock:
+                m = free_masks[k].pop() if free_masks[k] else None
+            if m is not None:
+                break
+            waited += 1
+            time.sleep(0.0002)
+        while True:
+            with lock:
+                t = srv.submit(x, win, m, tag=k)
+                if t is not None:
+                    pending[t] = (arr_ns, k, m, cells)
+                    break
+            eagain += 1
+            time.sleep(0.0002)
+    srv.shutdown(drain=True)
+    t_end = time.monotonic_ns()
+    with lock:
+        stop[0] = True
+    th.join(timeout=60)
+    st = srv.stats()
+    srv.close()
+    wall = (t_end - t0) / 1e9
+    return {"seconds": round(wall, 2), "streams": n_streams, "rate_hz_per_stream": 50.0,
+            "frame_sizes": "%dx%d .. %dx%d FP32" % (streams[0]["rows"], streams[0]["cols"], streams[-1]["rows"],
+                                                   streams[-1]["cols"]),
+            "frames": len(lat_ms), "failed": int(st.failed), "batches": int(st.batches),
+            "mean_frames_per_batch": round(len(lat_ms) / max(1, int(st.batches)), 2),
+            "p50_ms": round(percentile(lat_ms, 50), 3) if lat_ms else None,
+            "p99_ms": round(percentile(lat_ms, 99), 3) if lat_ms else None,
+            "max_ms": round(max(lat_ms), 3) if lat_ms else None,
+            "cells_per_s": done_cells[0] / wall, "eagain": eagain, "mask_waits": waited,
+            "device_bytes_peak": int(st.device_bytes_peak)}
 
 
 def build_workload(name):
@@ -125,7 +270,19 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the tiled form only (for rocprofv3)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device 3 times (the counter scale of rocprofv3 FETCH_SIZE "
+                         "and WRITE_SIZE)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the serving run (16 Poisson streams at 50 Hz); 0 skips it")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the traffic file from rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
+    if args.record_traffic:
+        record_traffic(*args.record_traffic, workload=args.workload,
+                       command="rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --profile-only "
+                               "--workload %s; copy scale from bench.py --copy-probe" % args.workload)
+        return
 
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -139,6 +296,14 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)   # an elementwise kernel: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
     C.lib()
 
     specs, desc = build_workload(args.workload)
@@ -157,9 +322,12 @@ def main():
     masks = [torch.empty(x.shape, dtype=torch.uint8, device=dev) for x in xs]
     batch = C.Batch(xs, wins, C.TILED, masks=masks)
     flags = 0 if args.no_graph else C.BATCH_GRAPH
-    stream = torch.cuda.current_stream()
+    # a stream of our own (default priority): the library captures and
+    # replays its graph, and forks kernel classes, only on a non-null stream
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
     for _ in range(args.warmup):
-        batch.run(flags)
+        batch.run(flags, stream=stream)
     torch.cuda.synchronize()
     log("timing %d steps" % args.steps)
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -167,7 +335,7 @@ def main():
     t0 = time.perf_counter()
     evs[0].record(stream)
     for k in range(args.steps):
-        batch.run(flags)
+        batch.run(flags, stream=stream)
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -184,7 +352,7 @@ def main():
     C.timing_enable(True)
     kms = []
     for _ in range(max(5, min(args.steps, 20))):
-        batch.run(0)
+        batch.run(0, stream=stream)
         kms.append(C.timing_read())
     C.timing_enable(False)
     kernel_ms = float(np.mean(kms))
@@ -206,12 +374,12 @@ def main():
     if not args.no_plain:
         pmasks = [torch.empty(x.shape, dtype=torch.uint8, device=dev) for x in xs]
         pbatch = C.Batch(xs, wins, C.PLAIN, masks=pmasks)
-        pbatch.run(0)
+        pbatch.run(0, stream=stream)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(args.plain_steps):
-            pbatch.run(0)
+            pbatch.run(0, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
         pms = e0.elapsed_time(e1) / args.plain_steps
@@ -219,6 +387,12 @@ def main():
         plain = {"ms_per_step": round(pms, 3), "cells_per_s": cells / (pms / 1e3),
                  "mask_cells_differing_from_tiled": diff}
         log("plain: %.3f ms/step (%d mask cells differ from tiled)" % (pms, diff))
+
+    serving = None
+    if args.serve_seconds > 0:
+        log("serving run, %.0f s" % args.serve_seconds)
+        serving = serve_bench(args.serve_seconds)
+        log("serving: p50 %s ms, p99 %s ms, %d frames" % (serving["p50_ms"], serving["p99_ms"], serving["frames"]))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -243,8 +417,12 @@ def main():
                    "graph": not args.no_graph, "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4),
-                       "what": "per batched launch, back-to-back"},
+        "latency_ms": ({"p50": serving["p50_ms"], "p99": serving["p99_ms"],
+                        "what": "serving: frame arrival to mask in host memory, 16 Poisson streams at 50 Hz"}
+                       if serving else None),
+        "launch_latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4),
+                              "what": "per batched launch, back-to-back"},
+        "serving": serving,
         "plain_form": plain,
         "speedup_vs_plain": (round(plain["ms_per_step"] / ms_per_step, 3) if plain else None),
         "effective_hbm_frac": round((in_bytes + cells) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

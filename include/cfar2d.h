@@ -63,10 +63,14 @@ typedef enum { CFAR_F32 = 0, CFAR_F64 = 1 } cfar_dtype;
 /* Precision forms.
  *   PLAIN: the integral image of eq. (3) is materialised in FP64 in device
  *          memory (by sat2d), then the eight-corner stencil of eq. (4) reads it.
- *   TILED: the integral image is never materialised.  Each work tile builds
- *          tile-local prefix sums of its own rows and columns (plus the window
- *          halo) with FP64 carries and evaluates the eight corners from them;
- *          the map stays in its storage type (FP32 or FP64).  One pass over X. */
+ *   TILED: the integral image is never materialised.  The eight corners of
+ *          eq. (4) are separable: each work unit (a strip of columns plus a
+ *          halo of guard_f + train_f + 1 columns, times a chunk of rows)
+ *          keeps FP64 running column sums over the outer and guard windows'
+ *          rows (the row corners) and takes an FP64 row prefix of them across
+ *          the strip (the column corners as differences).  The map stays in
+ *          its storage type (FP32 or FP64); one pass over X.  Supports
+ *          guard_f + train_f <= 247. */
 typedef enum { CFAR_FORM_PLAIN = 0, CFAR_FORM_TILED = 1 } cfar_form;
 
 /* CFAR window (Table I, eq. 2): half-widths per axis, in cells.  The outer
@@ -148,10 +152,14 @@ enum {
 };
 
 /* CA-CFAR over `n` maps of any sizes, each with its own window and Pfa.
- * maps: host array of n descriptors.  TILED: one persistent launch over the
- * work tiles of all maps (plus one small kernel that builds the threshold
- * tables); each map's tile shape depends only on that map's own size, window
- * and dtype, so every map's result is the same alone and in any batch.
+ * maps: host array of n descriptors.  TILED: one small kernel builds the
+ * threshold tables, then one persistent launch per kernel class runs the work
+ * units of all maps of that class (classes: k_cols 2 or 4 / 8, dtype, with or
+ * without the optional outputs -- FP32 maps without optional outputs are one
+ * launch); on a non-NULL stream, classes after the first run on the
+ * library's own streams forked from and joined back into `stream`.  Each
+ * map's tile plan depends only on that map's own size, window and dtype, so
+ * every map's result is the same alone and in any batch.
  * PLAIN: the per-map FP64 form, one sat2d + stencil per map on `stream`.
  * Errors as cfar2d; map k's problems are reported with its index. */
 int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags, void *ws,
@@ -163,15 +171,22 @@ int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags,
 
 typedef struct {
     int32_t k_cols;        /* columns per lane: 2, 4 or 8 (a 64-lane wave covers 64*k_cols cols) */
-    int32_t rows_per_unit; /* output rows per work unit, 8..4096                                  */
+    int32_t rows_per_unit; /* output rows per work unit, 1..4096                                  */
+    int32_t ring_bytes;    /* LDS bytes per wave for the ring of recent rows, 0..65536, or -1 for
+                            * the library default.  The ring holds either every row of the
+                            * window (one global load per row) or only the guard rows (three),
+                            * whichever fits; 0 = no ring (five).  Results do not depend on it. */
 } cfar_plan;
 
 /* The plan the TILED form uses for map m (from the loaded table, else the
  * built-in cost model).  Depends only on m's dtype, rows, cols and window. */
 int cfar_plan_for(const cfar_map *m, cfar_plan *out);
 
-/* Load a plan table written by the autotuner (text; one rule per line, see
- * paper_2012_11077_amd/autotune.py).  NULL or "" restores the built-in model.
+/* Load a plan table written by the autotuner (text; one rule per line:
+ *   dtype cols_lo cols_hi rows_lo rows_hi hf_lo hf_hi hr_lo hr_hi k rows_per_unit [ring_bytes]
+ * with dtype f32 | f64 | any, '#' starting a comment, first matching rule
+ * winning; see paper_2012_11077_amd/autotune.py).  NULL or "" restores the
+ * built-in model.
  * Not thread-safe with concurrent TILED calls. */
 int cfar_plan_load(const char *path);
 

@@ -51,7 +51,7 @@ class Map(ctypes.Structure):
 
 
 class Plan(ctypes.Structure):
-    _fields_ = [("k_cols", ctypes.c_int32), ("rows_per_unit", ctypes.c_int32)]
+    _fields_ = [("k_cols", ctypes.c_int32), ("rows_per_unit", ctypes.c_int32), ("ring_bytes", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -99,17 +99,18 @@ def lib():
         L.cfar_plan_for.argtypes = [_PMap, ctypes.POINTER(Plan)]
         L.cfar_plan_load.argtypes = [ctypes.c_char_p]
         L.cfar2d_with_plan.argtypes = [_PMap, ctypes.POINTER(Plan), _vp, _sz, _vp]
-        if hasattr(L, "cfar_server_create"):
-            L.cfar_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
-            L.cfar_submit.argtypes = [_vp, _PMap, _i32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
-            L.cfar_poll.argtypes = [_vp, ctypes.POINTER(Completion), _i32, _i32, ctypes.POINTER(_i32)]
-            L.cfar_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
-            L.cfar_server_shutdown.argtypes = [_vp, _i32]
-            L.cfar_server_destroy.argtypes = [_vp]
+        L.cfar_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
+        L.cfar_submit.argtypes = [_vp, _PMap, _i32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]
+        L.cfar_poll.argtypes = [_vp, ctypes.POINTER(Completion), _i32, _i32, ctypes.POINTER(_i32)]
+        L.cfar_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+        L.cfar_server_shutdown.argtypes = [_vp, _i32]
+        L.cfar_server_destroy.argtypes = [_vp]
         L.cfar_timing_enable.argtypes = [_i32]
         L.cfar_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
         for name in ("sat2d", "cfar2d", "cfar2d_batched", "cfar_plan_for", "cfar_plan_load",
-                     "cfar2d_with_plan", "cfar_timing_enable", "cfar_timing_read"):
+                     "cfar2d_with_plan", "cfar_timing_enable", "cfar_timing_read", "cfar_server_create",
+                     "cfar_submit", "cfar_poll", "cfar_server_stats_get", "cfar_server_shutdown",
+                     "cfar_server_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         table = os.environ.get("CFAR2D_PLAN_TABLE")
@@ -260,14 +261,15 @@ def cfar2d(x: torch.Tensor, window, form: int = TILED, mask: Optional[torch.Tens
 
 def cfar2d_with_plan(x: torch.Tensor, window, k_cols: int, rows_per_unit: int,
                      mask: Optional[torch.Tensor] = None, train_sum=None, threshold=None,
-                     ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """TILED CA-CFAR with an explicit tile plan (autotuner probe)."""
+                     ws: Optional[torch.Tensor] = None, stream=None, ring_bytes: int = -1) -> torch.Tensor:
+    """TILED CA-CFAR with an explicit tile plan (autotuner probe); ring_bytes
+    -1 takes the library default."""
     if mask is None:
         mask = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
     m = make_map(x, window, mask, train_sum, threshold)
     if ws is None:
         ws = _alloc_ws(workspace_bytes([m], TILED), x.device)
-    p = Plan(int(k_cols), int(rows_per_unit))
+    p = Plan(int(k_cols), int(rows_per_unit), int(ring_bytes))
     _check(lib().cfar2d_with_plan(ctypes.byref(m), ctypes.byref(p), ws.data_ptr(), ws.numel(),
                                   _stream_handle(stream)))
     return mask
@@ -310,12 +312,12 @@ def cfar2d_batched(xs: Sequence[torch.Tensor], windows: Sequence, form: int = TI
     return b.run(flags, stream)
 
 
-def plan_for(x: torch.Tensor, window) -> Tuple[int, int]:
-    """(k_cols, rows_per_unit) the TILED form uses for this map."""
+def plan_for(x: torch.Tensor, window) -> Tuple[int, int, int]:
+    """(k_cols, rows_per_unit, ring_bytes) the TILED form uses for this map."""
     m = make_map(x, window, _mask_like(x))
     p = Plan()
     _check(lib().cfar_plan_for(ctypes.byref(m), ctypes.byref(p)))
-    return int(p.k_cols), int(p.rows_per_unit)
+    return int(p.k_cols), int(p.rows_per_unit), int(p.ring_bytes)
 
 
 def _mask_like(x: torch.Tensor) -> torch.Tensor:
@@ -336,3 +338,57 @@ def timing_read() -> float:
 
 def plan_load(path: Optional[str]) -> None:
     _check(lib().cfar_plan_load(path.encode() if path else None))
+
+
+class Server:
+    """The library's streaming server (continuous batching of frames from
+    many streams).  Frames are either device tensors or host tensors (pinned
+    memory lets the copies overlap); the caller keeps each frame's tensors
+    alive until its ticket completes."""
+
+    def __init__(self, device_budget_bytes: int = 8 << 30, max_inflight_frames: int = 64,
+                 n_hip_streams: int = 4, queue_depth: int = 256, max_batch_frames: int = 32):
+        o = ServerOpts(int(device_budget_bytes), int(max_inflight_frames), int(n_hip_streams),
+                       int(queue_depth), int(max_batch_frames))
+        self._h = ctypes.c_void_p()
+        _check(lib().cfar_server_create(ctypes.byref(o), ctypes.byref(self._h)))
+
+    def submit(self, x: torch.Tensor, window, mask: torch.Tensor, tag: int = 0, train_sum=None,
+               threshold=None) -> Optional[int]:
+        """Ticket of the submitted frame, or None when the queue is full
+        (CFAR_EAGAIN).  Other errors raise."""
+        on_host = x.device.type == "cpu"
+        if (mask.device.type == "cpu") != on_host:
+            raise ValueError("x and mask must both be on the host or both on the device")
+        m = make_map(x, window, mask, train_sum, threshold)
+        t = ctypes.c_uint64()
+        rc = lib().cfar_submit(self._h, ctypes.byref(m), 1 if on_host else 0, int(tag), ctypes.byref(t))
+        if rc == CFAR_EAGAIN:
+            return None
+        _check(rc)
+        return int(t.value)
+
+    def poll(self, max_n: int = 64, timeout_us: int = 0) -> List[Completion]:
+        buf = (Completion * max_n)()
+        n = ctypes.c_int32()
+        _check(lib().cfar_poll(self._h, buf, int(max_n), int(timeout_us), ctypes.byref(n)))
+        return [buf[i] for i in range(n.value)]
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(lib().cfar_server_stats_get(self._h, ctypes.byref(st)))
+        return st
+
+    def shutdown(self, drain: bool = True) -> None:
+        _check(lib().cfar_server_shutdown(self._h, 1 if drain else 0))
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().cfar_server_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -108,9 +109,12 @@ static size_t lut_bytes(const cfar_map *m) { return align_up((size_t)(n_full_of(
 // ---------------------------------------------------------------------------
 struct Plan {
     int k, rs, H, tw, n_strips, n_rchunks;
+    int ring_bytes;  // LDS ring budget per wave (resolved: >= 0)
 };
 
-static bool plan_geometry(const cfar_map *m, int k, int rs, Plan *p)
+static int ring_budget();
+
+static bool plan_geometry(const cfar_map *m, int k, int rs, Plan *p, int ring_bytes = -1)
 {
     const int hf = m->win.guard_f + m->win.train_f;
     // >= hf + 1 (every prefix read stays inside the strip) and a multiple of
@@ -125,6 +129,7 @@ static bool plan_geometry(const cfar_map *m, int k, int rs, Plan *p)
     p->tw = tw;
     p->n_strips = (int)((m->cols + tw - 1) / tw);
     p->n_rchunks = (int)((m->rows + rs - 1) / rs);
+    p->ring_bytes = ring_bytes >= 0 ? ring_bytes : ring_budget();
     return true;
 }
 
@@ -132,32 +137,40 @@ struct PlanRule {
     int dtype;                    // -1 = any
     int64_t c_lo, c_hi, r_lo, r_hi;
     int hf_lo, hf_hi, hr_lo, hr_hi;
-    int k, rs;
+    int k, rs, ring_bytes;
 };
 static std::mutex g_plan_mu;
 static std::vector<PlanRule> g_rules;
 
-// Built-in cost model: VALU work per processed column-row for each k (scan
-// cost amortised over k columns), times the columns the strips cover.
+// Built-in cost model (fitted to timings of one wave per strip row on
+// gfx950): a strip row costs c(k) with c(2) = 0.5, c(4) = 1, c(8) = 3
+// (c(2) = 0.45 when k = 2 can hold every window row in its LDS ring and k = 4
+// cannot); a map narrower than one strip whose last column falls inside a
+// lane takes the general path, about three times the cost.  64 rows per unit
+// keeps the persistent launch's tail short.
 static cfar_plan default_plan(const cfar_map *m)
 {
     const int hr = m->win.guard_r + m->win.train_r;
     static const int ks[3] = {2, 4, 8};
-    static const double col_cost[3] = {42.0, 32.0, 27.0};
     double best = 1e300;
-    int bk = 8;
+    int bk = 4;
     for (int t = 0; t < 3; ++t) {
+        const int k = ks[t];
         Plan p;
-        if (!plan_geometry(m, ks[t], 64, &p)) continue;
-        const double cost = (double)p.n_strips * 64.0 * ks[t] * col_cost[t];
-        if (cost < best * 0.999) { best = cost; bk = ks[t]; }
+        if (!plan_geometry(m, k, 64, &p)) continue;
+        const bool ring2 = 2 * hr + 2 <= ring_rows_cap(2, m->dtype, ring_budget());
+        const bool ring4 = 2 * hr + 2 <= ring_rows_cap(4, m->dtype, ring_budget());
+        const double c = k == 2 ? (ring2 && !ring4 ? 0.45 : 0.5) : k == 4 ? 1.0 : 3.0;
+        double cost = (double)p.n_strips * c;
+        // a map narrower than one strip whose last column falls inside a
+        // lane takes the general path
+        if (m->cols % k != 0 && m->cols + p.H < 64 * k) cost *= 3.0;
+        if (cost < best * 0.999) { best = cost; bk = k; }
     }
-    int rs = std::max(64, ((4 * hr + 15) / 16) * 16);
-    rs = std::min(rs, 512);
-    if (rs > m->rows) rs = (int)m->rows;
     cfar_plan out;
     out.k_cols = bk;
-    out.rows_per_unit = rs;
+    out.rows_per_unit = (int)std::min<int64_t>(64, m->rows);
+    out.ring_bytes = -1;
     return out;
 }
 
@@ -175,6 +188,7 @@ static cfar_plan choose_plan(const cfar_map *m)
             cfar_plan out;
             out.k_cols = r.k;
             out.rows_per_unit = (int)std::min<int64_t>(r.rs, m->rows);
+            out.ring_bytes = r.ring_bytes;
             return out;
         }
     }
@@ -185,6 +199,7 @@ static bool plan_valid(const cfar_map *m, const cfar_plan *p)
 {
     if (!(p->k_cols == 2 || p->k_cols == 4 || p->k_cols == 8)) return false;
     if (p->rows_per_unit < 1 || p->rows_per_unit > 4096) return false;
+    if (p->ring_bytes < -1 || p->ring_bytes > 65536) return false;
     Plan g;
     return plan_geometry(m, p->k_cols, p->rows_per_unit, &g);
 }
@@ -222,7 +237,10 @@ static MapDesc make_desc(const cfar_map *m, const Plan *p, double *lut)
         const size_t es = m->dtype == CFAR_F32 ? 4 : 8;
         const bool x_vec = ((uintptr_t)m->x % 16 == 0) && ((m->ld * (int64_t)es) % 16 == 0);
         const bool m_vec = ((uintptr_t)m->mask % 4 == 0) && (m->ld_mask % 4 == 0);
-        d.vec_ok = (x_vec ? 1 : 0) | (m_vec ? 2 : 0);
+        // bit 4: the rows one work unit reads span fewer than 2^31 bytes, so
+        // the interior loop can address them through one buffer resource
+        const double span = ((double)p->rs + 2.0 * d.hr + 2.0) * (double)m->ld * (double)es;
+        d.vec_ok = (x_vec ? 1 : 0) | (m_vec ? 2 : 0) | (span < 2147483647.0 ? 4 : 0);
     }
     return d;
 }
@@ -260,16 +278,36 @@ static TiledLayout tiled_layout(const cfar_map *maps, int n, uint64_t total_unit
     return L;
 }
 
+// LDS bytes per wave for the TILED kernel's row ring (CFAR2D_RING_BYTES
+// overrides the default, for tuning).
+static int ring_budget()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = std::getenv("CFAR2D_RING_BYTES");
+        v = e ? std::max(0, std::atoi(e)) : kDefaultRingBytes;
+    }
+    return v;
+}
+
 // Maps of one kernel class (columns per lane k, dtype) and their work units.
 struct KClass {
-    int k, dtype;
-    bool out;  // maps of the class may write the optional outputs
+    int kset, dtype;  // kset 24: maps planned with k = 2 or 4; 8: k = 8
+    bool out;         // maps of the class may write the optional outputs
     uint32_t unit_off, units, blocks;
+    int ring_bytes;   // LDS ring per wave of its launch (largest need among the maps)
 };
-static int class_slot(int k, int dtype, bool out) { return ((k == 2 ? 0 : k == 4 ? 1 : 2) * 2 + dtype) + (out ? 6 : 0); }
+static int class_slot(int kset, int dtype, bool out) { return ((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0); }
 static bool has_outputs(const cfar_map *m) { return m->train_sum != nullptr || m->threshold != nullptr; }
 
 static uint64_t units_of(const Plan &p) { return (uint64_t)p.n_strips * (uint64_t)p.n_rchunks; }
+
+// LDS ring bytes map m needs under its plan's budget.
+static int map_ring_bytes(const cfar_map *m, const Plan &p)
+{
+    const int hr = m->win.guard_r + m->win.train_r;
+    return ring_bytes_needed(p.k, m->dtype, hr, m->win.guard_r, p.ring_bytes);
+}
 
 // ---------------------------------------------------------------------------
 // Batch contexts: pinned staging buffers (double-buffered per stream and
@@ -286,14 +324,71 @@ struct Slot {
     size_t sig_head = 0;
     uint64_t sig_layout = 0;
     uint32_t sig_units = 0, sig_n = 0;
+    ~Slot()
+    {
+        if (recorded && done) (void)hipEventSynchronize(done);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (done) (void)hipEventDestroy(done);
+        if (pinned) (void)hipHostFree(pinned);
+    }
 };
+// Kernel classes after the first run on side streams forked from (and
+// joined back into) the caller's stream, so a small class fills the tail of
+// a large one.
+constexpr int kSideStreams = 5;
 struct BatchCtx {
     Slot slot[2];
     int next = 0;
     std::mutex mu;
+    hipStream_t side[kSideStreams] = {};
+    hipEvent_t fork = nullptr, join[kSideStreams] = {};
+    ~BatchCtx()
+    {
+        for (int i = 0; i < kSideStreams; ++i) {
+            if (side[i]) (void)hipStreamDestroy(side[i]);
+            if (join[i]) (void)hipEventDestroy(join[i]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+    }
+    int ensure_side(int n)
+    {
+        if (!fork) {
+            hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_error(e, "hipEventCreate(fork)");
+        }
+        for (int i = 0; i < n && i < kSideStreams; ++i) {
+            if (!side[i]) {
+                hipError_t e = hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking);
+                if (e != hipSuccess) return hip_error(e, "hipStreamCreate(side)");
+            }
+            if (!join[i]) {
+                hipError_t e = hipEventCreateWithFlags(&join[i], hipEventDisableTiming);
+                if (e != hipSuccess) return hip_error(e, "hipEventCreate(join)");
+            }
+        }
+        return CFAR_OK;
+    }
 };
 static std::mutex g_ctx_mu;
-static std::map<std::pair<void *, void *>, std::unique_ptr<BatchCtx>> g_ctx;
+// Never destroyed: contexts hold HIP objects, which must not be released
+// from static destructors after the runtime has gone at process exit.
+static auto &g_ctx = *new std::map<std::pair<void *, void *>, std::unique_ptr<BatchCtx>>();
+
+// Forget the batch context of (stream, ws): its staging buffers, graphs and
+// side streams are freed once its last batch has finished.
+void drop_batch_ctx(hipStream_t s, void *ws)
+{
+    std::unique_ptr<BatchCtx> p;
+    {
+        std::lock_guard<std::mutex> lk(g_ctx_mu);
+        auto it = g_ctx.find(std::make_pair((void *)s, ws));
+        if (it == g_ctx.end()) return;
+        p = std::move(it->second);
+        g_ctx.erase(it);
+    }
+    std::lock_guard<std::mutex> lk(p->mu);
+}
 
 static BatchCtx *get_ctx(hipStream_t s, void *ws)
 {
@@ -328,7 +423,7 @@ static int slot_reserve(Slot &sl, size_t bytes)
 }
 
 // Enqueue: descriptor copy, table kernel, one persistent kernel per class.
-static int enqueue_tiled_batch(const Slot &sl, const TiledLayout &L, char *ws, uint32_t n,
+static int enqueue_tiled_batch(BatchCtx *ctx, const Slot &sl, const TiledLayout &L, char *ws, uint32_t n,
                                const std::vector<KClass> &classes, hipStream_t stream)
 {
     hipError_t e = hipMemcpyAsync(ws, sl.pinned, L.head_bytes, hipMemcpyHostToDevice, stream);
@@ -341,18 +436,40 @@ static int enqueue_tiled_batch(const Slot &sl, const TiledLayout &L, char *ws, u
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
     e = timing_mark(g_timing.start, stream);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
-    for (const KClass &c : classes) {
+    // classes 1.. on side streams (a stream with the default handle has no
+    // side streams: it serialises with every other stream anyway)
+    const int n_side = stream ? std::min<int>((int)classes.size() - 1, kSideStreams) : 0;
+    if (n_side > 0) {
+        int rc = ctx->ensure_side(n_side);
+        if (rc != CFAR_OK) return rc;
+        e = hipEventRecord(ctx->fork, stream);
+        if (e != hipSuccess) return hip_error(e, "hipEventRecord(fork)");
+        for (int i = 0; i < n_side; ++i) {
+            e = hipStreamWaitEvent(ctx->side[i], ctx->fork, 0);
+            if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent(fork)");
+        }
+    }
+    for (size_t ci = 0; ci < classes.size(); ++ci) {
+        const KClass &c = classes[ci];
+        const int si = (int)ci - 1;
+        hipStream_t cs = (si >= 0 && si < n_side) ? ctx->side[si] : stream;
         FusedArgs a;
         std::memset(&a, 0, sizeof a);
         a.descs = descs;
         a.unit_base = (const uint32_t *)(ws + L.off_base);
         a.unit_map = (const uint32_t *)(ws + L.off_umap) + c.unit_off;
-        a.counter = &hdr->counter[class_slot(c.k, c.dtype, c.out)];
-        a.sink = hdr->sink;
+        a.counter = &hdr->counter[class_slot(c.kset, c.dtype, c.out)];
         a.total_units = c.units;
         a.n_maps = n;
-        e = launch_fused(a, c.k, c.dtype, c.out, stream);
+        a.ring_bytes = c.ring_bytes;
+        e = launch_fused(a, c.kset, c.dtype, c.out, cs);
         if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
+    }
+    for (int i = 0; i < n_side; ++i) {
+        e = hipEventRecord(ctx->join[i], ctx->side[i]);
+        if (e != hipSuccess) return hip_error(e, "hipEventRecord(join)");
+        e = hipStreamWaitEvent(stream, ctx->join[i], 0);
+        if (e != hipSuccess) return hip_error(e, "hipStreamWaitEvent(join)");
     }
     e = timing_mark(g_timing.stop, stream);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
@@ -367,7 +484,7 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
     uint64_t total_units = 0;
     for (int i = 0; i < n; ++i) {
         cfar_plan cp = forced ? *forced : choose_plan(&maps[i]);
-        if (!plan_geometry(&maps[i], cp.k_cols, cp.rows_per_unit, &plans[i]))
+        if (!plan_geometry(&maps[i], cp.k_cols, cp.rows_per_unit, &plans[i], cp.ring_bytes))
             return set_error(CFAR_EINVAL, "map %d: no valid tile plan", i);
         total_units += units_of(plans[i]);
     }
@@ -383,18 +500,21 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
     std::vector<KClass> classes;
     std::vector<std::vector<int>> members;
     for (int i = 0; i < n; ++i) {
-        const int k = plans[i].k, dt = maps[i].dtype;
+        const int ks = kset_of(plans[i].k), dt = maps[i].dtype;
         const bool out = has_outputs(&maps[i]);
         size_t c = 0;
-        while (c < classes.size() && !(classes[c].k == k && classes[c].dtype == dt && classes[c].out == out)) ++c;
+        while (c < classes.size() && !(classes[c].kset == ks && classes[c].dtype == dt && classes[c].out == out)) ++c;
         if (c == classes.size()) {
             KClass kc;
-            kc.k = k; kc.dtype = dt; kc.out = out; kc.unit_off = 0; kc.units = 0; kc.blocks = 0;
+            kc.kset = ks; kc.dtype = dt; kc.out = out; kc.unit_off = 0; kc.units = 0; kc.blocks = 0;
+            kc.ring_bytes = 0;
             classes.push_back(kc);
             members.emplace_back();
         }
         members[c].push_back(i);
         classes[c].units += (uint32_t)units_of(plans[i]);
+        if (!out)
+            classes[c].ring_bytes = std::max(classes[c].ring_bytes, map_ring_bytes(&maps[i], plans[i]));
     }
     {
         std::vector<size_t> corder(classes.size());
@@ -411,8 +531,9 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
     for (size_t c = 0; c < classes.size(); ++c) {
         classes[c].unit_off = off;
         off += classes[c].units;
-        const int resident = fused_resident_blocks(classes[c].k, classes[c].dtype, classes[c].out);
-        classes[c].blocks = (uint32_t)std::min<uint64_t>((classes[c].units + 3) / 4, (uint64_t)resident);
+        const int resident =
+            fused_resident_blocks(classes[c].kset, classes[c].dtype, classes[c].out, classes[c].ring_bytes);
+        classes[c].blocks = (uint32_t)std::min<uint64_t>(classes[c].units, (uint64_t)resident);
         std::stable_sort(members[c].begin(), members[c].end(),
                          [&](int a, int b) { return units_of(plans[a]) > units_of(plans[b]); });
     }
@@ -443,7 +564,8 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
     }
     uint64_t sig = 1469598103934665603ull;  // FNV-1a over the class layout
     for (const KClass &c : classes) {
-        const uint32_t f[6] = {(uint32_t)c.k, (uint32_t)c.dtype, (uint32_t)c.out, c.unit_off, c.units, c.blocks};
+        const uint32_t f[7] = {(uint32_t)c.kset, (uint32_t)c.dtype,  (uint32_t)c.out,      c.unit_off,
+                               c.units,            c.blocks,           (uint32_t)c.ring_bytes};
         for (uint32_t v : f) { sig ^= v; sig *= 1099511628211ull; }
     }
 
@@ -456,7 +578,7 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
             if (sl.graph) { (void)hipGraphDestroy(sl.graph); sl.graph = nullptr; }
             hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-            rc = enqueue_tiled_batch(sl, L, (char *)ws, (uint32_t)n, classes, stream);
+            rc = enqueue_tiled_batch(ctx, sl, L, (char *)ws, (uint32_t)n, classes, stream);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(stream, &g);
             if (rc != CFAR_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
@@ -472,7 +594,7 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
         hipError_t e = hipGraphLaunch(sl.exec, stream);
         if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
     } else {
-        rc = enqueue_tiled_batch(sl, L, (char *)ws, (uint32_t)n, classes, stream);
+        rc = enqueue_tiled_batch(ctx, sl, L, (char *)ws, (uint32_t)n, classes, stream);
         if (rc != CFAR_OK) return rc;
     }
     hipError_t e = hipEventRecord(sl.done, stream);
@@ -486,7 +608,8 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
 static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     Plan p;
-    if (!plan_geometry(m, cp.k_cols, cp.rows_per_unit, &p)) return set_error(CFAR_EINVAL, "no valid tile plan");
+    if (!plan_geometry(m, cp.k_cols, cp.rows_per_unit, &p, cp.ring_bytes))
+        return set_error(CFAR_EINVAL, "no valid tile plan");
     const size_t need = sizeof(BatchHeader) + lut_bytes(m);
     if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
     if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
@@ -499,14 +622,14 @@ static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, si
     std::memset(&a, 0, sizeof a);
     a.single = make_desc(m, &p, lut);
     a.counter = counter;
-    a.sink = hdr->sink;
     a.total_units = (uint32_t)units;
     a.n_maps = 1;
+    a.ring_bytes = has_outputs(m) ? 0 : map_ring_bytes(m, p);
     hipError_t e = launch_lut(nullptr, a.single, 1, counter, stream);
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
     e = timing_mark(g_timing.start, stream);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
-    e = launch_fused(a, p.k, m->dtype, has_outputs(m), stream);
+    e = launch_fused(a, kset_of(p.k), m->dtype, has_outputs(m), stream);
     if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
     e = timing_mark(g_timing.stop, stream);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
@@ -682,7 +805,7 @@ int cfar_plan_for(const cfar_map *m, cfar_plan *out)
 }
 
 // Plan table: one rule per line,
-//   dtype cols_lo cols_hi rows_lo rows_hi hf_lo hf_hi hr_lo hr_hi k rows_per_unit
+//   dtype cols_lo cols_hi rows_lo rows_hi hf_lo hf_hi hr_lo hr_hi k rows_per_unit [ring_bytes]
 // dtype = f32 | f64 | any; '#' starts a comment.  First matching rule wins.
 int cfar_plan_load(const char *path)
 {
@@ -703,6 +826,9 @@ int cfar_plan_load(const char *path)
             long long c0, c1, r0, r1;
             if (!(is >> c0 >> c1 >> r0 >> r1 >> r.hf_lo >> r.hf_hi >> r.hr_lo >> r.hr_hi >> r.k >> r.rs))
                 return set_error(CFAR_EINVAL, "%s:%d: malformed rule", path, ln);
+            if (!(is >> r.ring_bytes)) r.ring_bytes = -1;
+            if (r.ring_bytes < -1 || r.ring_bytes > 65536)
+                return set_error(CFAR_EINVAL, "%s:%d: ring_bytes must be -1 or in [0, 65536]", path, ln);
             r.c_lo = c0; r.c_hi = c1; r.r_lo = r0; r.r_hi = r1;
             if (dt == "f32") r.dtype = 0;
             else if (dt == "f64") r.dtype = 1;

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "cfar2d.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -33,7 +35,7 @@ struct MapDesc {
     int32_t n_strips;     // TILED: strips across the columns
     int32_t n_rchunks;    // TILED: row chunks
     int32_t n_full;       // training cells of an unclipped window
-    int32_t vec_ok;       // 1: x rows and mask rows allow aligned vector access
+    int32_t vec_ok;       // bits: 1 x rows aligned, 2 mask rows aligned, 4 unit row span < 2^31 bytes
     int32_t pad0;
 };
 static_assert(sizeof(MapDesc) == 128, "MapDesc must stay 128 bytes");
@@ -45,9 +47,10 @@ struct FusedArgs {
     const uint32_t *unit_map;  // map index of every work unit (device), or nullptr
     const uint32_t *unit_base; // first work unit of every map (device), or nullptr
     uint32_t *counter;         // work counter (device), zeroed by the table kernel
-    uint32_t *sink;            // 512 bytes of device scratch: stores of lanes without outputs
     uint32_t total_units;
     uint32_t n_maps;
+    int32_t ring_bytes;        // LDS bytes per wave for the row ring (see ring_rows_cap)
+    int32_t pad;
     MapDesc single;
 };
 
@@ -59,9 +62,8 @@ struct BatchHeader {
     uint32_t n_maps;
     uint32_t total_units;
     uint32_t pad[46];
-    uint32_t sink[128];    // stores of lanes without outputs land here
 };
-static_assert(sizeof(BatchHeader) == 768, "BatchHeader must stay 768 bytes");
+static_assert(sizeof(BatchHeader) == 256, "BatchHeader must stay 256 bytes");
 
 // SAT tile geometry of the PLAIN form: 32 rows x 256 columns per workgroup.
 constexpr int kSatTH = 32;
@@ -86,6 +88,12 @@ SatWs sat_ws_layout(void *ws, int64_t rows, int64_t cols);
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Host-side helpers shared by the library's translation units.
+int set_error(int code, const char *fmt, ...);
+int hip_error(hipError_t e, const char *what);
+int validate_map(const cfar_map *m, int idx, int form);
+void drop_batch_ctx(hipStream_t s, void *ws);
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All enqueue on `stream` and return the
 // hipError_t of the launch.
@@ -104,15 +112,47 @@ hipError_t launch_lut(const MapDesc *descs, const MapDesc &single, int n, uint32
 // Eight-corner stencil over the PLAIN FP64 SAT of one map.
 hipError_t launch_stencil_plain(const MapDesc &d, const double *sat, hipStream_t stream);
 
-// Persistent TILED kernel (columns per lane k, map dtype, out = maps may
-// carry the optional training-sum / threshold outputs) over all work units
-// in `args`; every map in `args` must belong to that class.
-hipError_t launch_fused(const FusedArgs &args, int k, int dtype, bool out, hipStream_t stream);
+// Persistent TILED kernel over all work units in `args`.  One kernel per
+// (k set, dtype, out): kset 24 serves maps planned with k = 2 or 4 (one
+// launch for both), kset 8 maps with k = 8; out = maps may carry the
+// optional training-sum / threshold outputs.
+hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, hipStream_t stream);
 
 // Number of persistent workgroups of that kernel that fit the device.
-int fused_resident_blocks(int k, int dtype, bool out);
+int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes);
 
-constexpr int kFusedThreads = 256;  // 4 independent waves per workgroup
+constexpr int kFusedThreads = 64;  // one wave per workgroup: LDS is sized per wave
 constexpr int kMaxK = 8;
+constexpr int kMaxRingRows = 64;
+constexpr int kDefaultRingBytes = 12288;
+
+inline int kset_of(int k) { return k == 8 ? 8 : 24; }
+inline int kmax_of(int kset) { return kset == 8 ? 8 : 4; }
+
+// Rows of 64*k values a ring of `ring_bytes` holds (at most kMaxRingRows).
+inline int ring_rows_cap(int k, int dtype, int ring_bytes)
+{
+    const int cap = ring_bytes / (64 * k * (dtype == 0 ? 4 : 8));
+    return cap < kMaxRingRows ? cap : kMaxRingRows;
+}
+
+// Ring bytes one map needs under a budget: every window row (2*hr+2 rows,
+// one global load per step) if they fit, else the guard rows (2*gr+2 rows,
+// three loads per step) if those fit, else none (five loads per step).
+inline int ring_bytes_needed(int k, int dtype, int hr, int gr, int budget)
+{
+    const int cap = ring_rows_cap(k, dtype, budget);
+    const int row = 64 * k * (dtype == 0 ? 4 : 8);
+    if (2 * hr + 2 <= cap) return (2 * hr + 2) * row;
+    if (2 * gr + 2 <= cap) return (2 * gr + 2) * row;
+    return 0;
+}
+
+// Dynamic LDS of one wave of the TILED kernel: two prefix rows of 64*kmax
+// doubles, then the ring.
+inline size_t fused_lds_bytes(int kset, int ring_bytes)
+{
+    return (size_t)2 * kmax_of(kset) * 64 * 8 + (size_t)ring_bytes;
+}
 
 }  // namespace cfar

@@ -183,10 +183,8 @@ def config3_specs(n: int = 512, seed: int = 3, rows=(200, 4096), cols=(64, 2048)
 def config4_streams(n_streams: int = 16, seed: int = 4) -> List[dict]:
     """The serving workload: ``n_streams`` drone streams, stream k emitting
     frames of (round(256 * 2**(4k/15)), round(128 * 2**(3k/15))) FP32 cells
-    (256 x 128 up to 4096 x 1024) at Poisson rate 50 Hz, with the clutter,
-    targets and window of the 16384^2 precision workload (log-normal sigma 2,
-    targets at 8-30 dB at the same density, guard 4x4, training 24x24,
-    Pfa 1e-5)."""
+    (256 x 128 up to 4096 x 1024) at Poisson rate 50 Hz; clutter, targets,
+    window and Pfa of each frame drawn as for the uneven batch."""
     out = []
     last = max(1, n_streams - 1)
     for k in range(n_streams):
@@ -197,11 +195,18 @@ def config4_streams(n_streams: int = 16, seed: int = 4) -> List[dict]:
 
 
 def stream_frame_spec(stream: dict, frame: int) -> MapSpec:
-    """Frame ``frame`` of a serving stream (seed (seed, stream, frame))."""
+    """Frame ``frame`` of a serving stream, drawn from seed
+    (seed, stream, frame) with the uneven batch's distributions: exponential
+    clutter with mean log-uniform in [0.1, 10], 0-20 targets at 10-25 dB,
+    per-axis guard in 1..4 and training in 4..24, Pfa in {1e-3, 1e-4, 1e-6}."""
     R, F = stream["rows"], stream["cols"]
-    nt = max(1, round(1000 * R * F / (16384 * 16384)))
-    return MapSpec(R, F, "f32", "lognormal", sigma=2.0, n_targets=nt, snr_lo_db=8.0,
-                   snr_hi_db=30.0, guard_r=4, guard_f=4, train_r=24, train_f=24, pfa=1e-5,
+    rng = _rng((stream["seed"], stream["stream"], frame, 7))
+    mean = float(np.exp(rng.uniform(math.log(0.1), math.log(10.0))))
+    gr, gf = (int(v) for v in rng.integers(1, 5, size=2))
+    tr, tf = (int(v) for v in rng.integers(4, 25, size=2))
+    pfa = float(rng.choice(np.array([1e-3, 1e-4, 1e-6])))
+    return MapSpec(R, F, "f32", "exp", mean, n_targets=int(rng.integers(0, 21)), snr_lo_db=10.0,
+                   snr_hi_db=25.0, guard_r=gr, guard_f=gf, train_r=tr, train_f=tf, pfa=pfa,
                    seed=(stream["seed"], stream["stream"], frame))
 
 

@@ -24,18 +24,26 @@ def _alloc(xs):
     return masks, sts
 
 
+@pytest.mark.parametrize("outputs", [True, False])
 @pytest.mark.parametrize("form", ["tiled", "plain"])
 @pytest.mark.parametrize("flags", [0, C.BATCH_GRAPH])
-def test_batched_parity(form, flags):
+def test_batched_parity(form, flags, outputs):
+    """Small uneven batch on a side stream (kernel classes fork onto the
+    library's own streams and join back), with and without the optional
+    training-sum output."""
     specs, xs_np = _small_batch()
     xs = [torch.from_numpy(x).to(DEV) for x in xs_np]
     masks, sts = _alloc(xs)
-    say("batched", form, flags, len(xs))
-    C.cfar2d_batched(xs, [s.window for s in specs], C.TILED if form == "tiled" else C.PLAIN,
-                     masks=masks, train_sums=sts, flags=flags)
+    say("batched", form, flags, outputs, len(xs))
+    side = torch.cuda.Stream()
     torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        C.cfar2d_batched(xs, [s.window for s in specs], C.TILED if form == "tiled" else C.PLAIN,
+                         masks=masks, train_sums=sts if outputs else None, flags=flags, stream=side)
+    side.synchronize()
     for k, s in enumerate(specs):
-        check_full(xs_np[k], s.window, masks[k].cpu().numpy(), sts[k].cpu().numpy(), None, form)
+        check_full(xs_np[k], s.window, masks[k].cpu().numpy(), sts[k].cpu().numpy() if outputs else None,
+                   None, form)
 
 
 def test_alone_equals_in_mix_and_order_free():

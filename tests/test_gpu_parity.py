@@ -172,3 +172,29 @@ def test_plans_give_the_same_answer():
             C.cfar2d_with_plan(x, spec.window, k, rs, mask=mask, train_sum=st)
             torch.cuda.synchronize()
             check_full(x_np, spec.window, mask.cpu().numpy(), st.cpu().numpy(), None, "tiled", ref=ref)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_ring_modes_agree(dtype):
+    """The interior loop's three row sources (every row from the LDS ring,
+    guard rows from the ring, no ring) give the same mask, bit for bit, and
+    match the oracle; windows chosen so each mode is taken for each k."""
+    for (g, t, cols) in [(1, 2, 1100), (2, 5, 1102), (4, 12, 1101), (2, 3, 1024)]:
+        # cols % 4 == 0, % 2 only, odd, % 8 == 0: border strips take the EDGE
+        # mode or the general one
+        spec = synth.MapSpec(600, cols, dtype, "exp", 1.0, n_targets=20, guard_r=g, guard_f=g, train_r=t,
+                             train_f=t, pfa=1e-4, seed=(21, g, t))
+        x_np = synth.generate(spec)
+        x = torch.from_numpy(x_np).to(DEV)
+        ref = oracle.cfar2d(x_np, *spec.window)
+        for k in (2, 4, 8):
+            masks = []
+            for ring in (0, 2 * 1024, 8 * 1024, 65536):
+                mask = torch.empty(x.shape, dtype=torch.uint8, device=DEV)
+                say("ring", dtype, g, t, k, ring)
+                C.cfar2d_with_plan(x, spec.window, k, 64, mask=mask, ring_bytes=ring)
+                torch.cuda.synchronize()
+                masks.append(mask.cpu().numpy())
+            check_full(x_np, spec.window, masks[0], None, None, "tiled", ref=ref)
+            for m in masks[1:]:
+                assert np.array_equal(m, masks[0])

@@ -1,0 +1,155 @@
+"""The streaming server (cfar_server_create / cfar_submit / cfar_poll /
+cfar_server_shutdown / cfar_server_destroy) on the GPU: each frame's result
+is the same alone and in the mix, back-pressure, admission by device
+memory, and both shutdown modes."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2012_11077_amd import cfar2d as C
+from paper_2012_11077_amd import synth
+from parity import check_full, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _frames(n, seed, rows=(40, 400), cols=(30, 500)):
+    specs = synth.config3_specs(n=n, seed=seed, rows=rows, cols=cols)
+    return specs, [synth.generate(s) for s in specs]
+
+
+def _alone(x_np, win):
+    x = torch.from_numpy(x_np).to(DEV)
+    m = torch.empty(x.shape, dtype=torch.uint8, device=DEV)
+    C.cfar2d(x, win, C.TILED, mask=m)
+    torch.cuda.synchronize()
+    return m.cpu().numpy()
+
+
+def _drain(srv, tickets, timeout_s=60.0):
+    got = {}
+    t_end = time.time() + timeout_s
+    while len(got) < len(tickets):
+        assert time.time() < t_end, "server did not complete %d frames" % (len(tickets) - len(got))
+        for c in srv.poll(64, 20000):
+            got[c.ticket] = c
+    return got
+
+
+def test_alone_equals_in_mix():
+    """Host (pinned) and device frames of many sizes, windows and Pfa,
+    submitted together over several HIP streams: every mask equals the one
+    the frame gets alone, and matches the oracle."""
+    specs, xs = _frames(40, seed=31)
+    ref = [_alone(x, s.window) for x, s in zip(xs, specs)]
+    with C.Server(device_budget_bytes=256 << 20, max_inflight_frames=16, n_hip_streams=3,
+                  queue_depth=64, max_batch_frames=6) as srv:
+        keep, tickets = [], {}
+        for k, (s, x) in enumerate(zip(specs, xs)):
+            if k % 2 == 0:   # host frame, pinned
+                xh = torch.from_numpy(x).pin_memory()
+                mh = torch.full(x.shape, 7, dtype=torch.uint8).pin_memory()
+            else:            # device frame
+                xh = torch.from_numpy(x).to(DEV)
+                mh = torch.full(x.shape, 7, dtype=torch.uint8, device=DEV)
+            torch.cuda.synchronize()
+            t = None
+            while t is None:
+                t = srv.submit(xh, s.window, mh, tag=k)
+            tickets[t] = k
+            keep.append((xh, mh))
+        say("server mix", len(tickets))
+        got = _drain(srv, tickets)
+        st = srv.stats()
+    torch.cuda.synchronize()
+    for t, c in got.items():
+        k = tickets[t]
+        assert c.status == C.CFAR_OK and c.user_tag == k
+        assert c.t_submit_ns <= c.t_start_ns <= c.t_done_ns
+        m = keep[k][1].cpu().numpy()
+        assert np.array_equal(m, ref[k]), k
+    for k in range(0, len(specs), 7):
+        check_full(xs[k], specs[k].window, keep[k][1].cpu().numpy())
+    assert st.completed == len(specs) and st.failed == 0
+    assert st.batches < len(specs)        # frames were batched together
+
+
+def test_backpressure_and_small_budget():
+    """A tiny queue gives CFAR_EAGAIN; a budget that holds only a few frames
+    admits them as memory frees up; every frame still completes."""
+    specs, xs = _frames(30, seed=32, rows=(200, 300), cols=(200, 300))
+    ref = [_alone(x, s.window) for x, s in zip(xs, specs)]
+    with C.Server(device_budget_bytes=2 << 20, max_inflight_frames=4, n_hip_streams=2,
+                  queue_depth=3, max_batch_frames=2) as srv:
+        keep, tickets, eagain = [], {}, 0
+        for k, (s, x) in enumerate(zip(specs, xs)):
+            xh = torch.from_numpy(x).pin_memory()
+            mh = torch.zeros(x.shape, dtype=torch.uint8).pin_memory()
+            keep.append((xh, mh))
+            while True:
+                t = srv.submit(xh, s.window, mh, tag=k)
+                if t is not None:
+                    tickets[t] = k
+                    break
+                eagain += 1
+                time.sleep(0.0005)
+        got = _drain(srv, tickets)
+        st = srv.stats()
+    assert eagain > 0
+    assert st.device_bytes_peak <= 2 << 20
+    for t, c in got.items():
+        assert c.status == C.CFAR_OK
+        assert np.array_equal(keep[tickets[t]][1].numpy(), ref[tickets[t]])
+
+
+def test_frame_larger_than_budget_is_rejected():
+    with C.Server(device_budget_bytes=1 << 20, max_inflight_frames=2, n_hip_streams=1,
+                  queue_depth=4, max_batch_frames=1) as srv:
+        x = torch.zeros((1024, 1024), dtype=torch.float32)
+        m = torch.zeros((1024, 1024), dtype=torch.uint8)
+        with pytest.raises(C.CfarError) as e:
+            srv.submit(x, (1, 1, 2, 2, 1e-3), m)
+        assert e.value.code == C.CFAR_EINVAL
+
+
+@pytest.mark.parametrize("drain", [True, False])
+def test_shutdown(drain):
+    """drain: queued frames run; no drain: they complete with
+    CFAR_ESHUTDOWN untouched.  Submits after shutdown are refused."""
+    specs, xs = _frames(24, seed=33, rows=(300, 600), cols=(300, 600))
+    srv = C.Server(device_budget_bytes=64 << 20, max_inflight_frames=2, n_hip_streams=1,
+                   queue_depth=64, max_batch_frames=1)
+    try:
+        keep, tickets = [], {}
+        for k, (s, x) in enumerate(zip(specs, xs)):
+            xh = torch.from_numpy(x).pin_memory()
+            mh = torch.full(x.shape, 9, dtype=torch.uint8).pin_memory()
+            keep.append((xh, mh))
+            t = srv.submit(xh, s.window, mh, tag=k)
+            assert t is not None
+            tickets[t] = k
+        srv.shutdown(drain=drain)
+        with pytest.raises(C.CfarError) as e:
+            srv.submit(keep[0][0], specs[0].window, keep[0][1])
+        assert e.value.code == C.CFAR_ESHUTDOWN
+        got = _drain(srv, tickets, timeout_s=10.0)
+    finally:
+        srv.close()
+    statuses = [c.status for c in got.values()]
+    if drain:
+        assert all(s == C.CFAR_OK for s in statuses)
+        for t, c in got.items():
+            k = tickets[t]
+            assert np.array_equal(keep[k][1].numpy(), _alone(xs[k], specs[k].window))
+    else:
+        assert set(statuses) <= {C.CFAR_OK, C.CFAR_ESHUTDOWN}
+        for t, c in got.items():
+            k = tickets[t]
+            if c.status == C.CFAR_ESHUTDOWN:   # never started: mask untouched
+                assert c.t_start_ns == 0
+                assert (keep[k][1].numpy() == 9).all()
+            else:
+                assert np.array_equal(keep[k][1].numpy(), _alone(xs[k], specs[k].window))
