@@ -352,9 +352,10 @@ __device__ __forceinline__ CFAR_GLOBAL T *gbl_w(T *p) { return (CFAR_GLOBAL T *)
 
 // Work-unit modes of the TILED kernel.  FAST: every lane's K columns lie
 // inside the map.  EDGE: a lane's K columns lie all inside or all outside the
-// map (a strip at the left or right border).  Both need 16-byte aligned map
-// rows and 4-byte aligned mask rows.  GENERAL: anything else.
-enum { kGeneral = 0, kEdge = 1, kFast = 2 };
+// map (a strip at the left or right border).  GENERAL: anything else.
+// kElem added to FAST or EDGE: the map's rows are not 16-byte aligned, so a
+// lane loads its K values one by one (still straight-line, no clamping).
+enum { kGeneral = 0, kEdge = 1, kFast = 2, kElem = 4 };
 
 // Loads of K consecutive values of one row (row: wave-uniform byte pointer)
 // starting at strip column c.  FAST: vector load.  EDGE: vector load, from
@@ -365,9 +366,12 @@ enum { kGeneral = 0, kEdge = 1, kFast = 2 };
 template <int K, typename T, int MODE>
 __device__ __forceinline__ void ldk(const CFAR_GLOBAL char *row, int c, int F, bool out, T (&v)[K])
 {
-    if constexpr (MODE != kGeneral) {
-        const uint32_t off = MODE == kEdge && out ? 0u : (uint32_t)c * (uint32_t)sizeof(T);
-        if constexpr (sizeof(T) == 4) {
+    if constexpr ((MODE & 3) != kGeneral) {
+        const uint32_t off = (MODE & 3) == kEdge && out ? 0u : (uint32_t)c * (uint32_t)sizeof(T);
+        if constexpr ((MODE & kElem) != 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = *(const CFAR_GLOBAL T *)(row + off + (uint32_t)(k * sizeof(T)));
+        } else if constexpr (sizeof(T) == 4) {
             if constexpr (K == 2) {
                 const f32x2 f = *(const CFAR_GLOBAL f32x2 *)(row + off);
                 v[0] = f.x; v[1] = f.y;
@@ -447,13 +451,22 @@ constexpr int warm_rows() { return K * sizeof(T) >= 32 ? 4 : 8; }
 constexpr int kBufferFlags = 0x00020000;
 
 // K consecutive values of one row through a buffer resource: lane byte
-// offset voff, wave-uniform row byte offset soff; 16-byte aligned.
-template <int K, typename T>
+// offset voff, wave-uniform row byte offset soff; 16-byte aligned, or
+// element by element (ELEM).
+template <int K, typename T, bool ELEM>
 __device__ __forceinline__ void ldk_buf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T (&v)[K])
 {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    if constexpr (K * sizeof(T) == 8) {
+    if constexpr (ELEM) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if constexpr (sizeof(T) == 4)
+                v[k] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 4u * k, soff, 0));
+            else
+                v[k] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 8u * k, soff, 0));
+        }
+    } else if constexpr (K * sizeof(T) == 8) {
         const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
         __builtin_memcpy(v, &w, 8);
     } else {
@@ -502,13 +515,14 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
     const int k_own0 = max(c_out0 - c_lane, 0);
     const bool lane_col_interior = (c_lane >= hf) && (c_lane + K - 1 + hf < F);
     // EDGE: a lane outside the map loads column 0 and weighs it by zero
-    const bool lane_outside = MODE == kEdge && (c_lane < 0 || c_lane >= F);
+    constexpr int BM = MODE & 3;  // FAST, EDGE or GENERAL
+    const bool lane_outside = BM == kEdge && (c_lane < 0 || c_lane >= F);
     const double lane_w = lane_outside ? 0.0 : 1.0;
     const double beta_full = gbl(d.lut)[d.n_full];
     // EDGE: beta per lane on rows without row clipping (NaN where N = 0: no
     // detection)
-    double beta_lane[MODE == kEdge ? K : 1];
-    if constexpr (MODE == kEdge) {
+    double beta_lane[BM == kEdge ? K : 1];
+    if constexpr (BM == kEdge) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int jc = min(max(c_lane + k, 0), F - 1);
@@ -591,14 +605,15 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         // column corners of eq. (4): box = Q(p + h) - Q(p - h - 1), outer minus inner
         return (rd_oh.get(qo, k) - rd_ol.get(qo, k)) - (rd_ih.get(qi, k) - rd_il.get(qi, k));
     };
+    // packed stores need 4-byte aligned mask rows and a strip start on a
+    // multiple of min(K, 4) columns; else bytes
+    const bool mvec = (d.vec_ok & 2) != 0 && (cs % (K < 4 ? K : 4)) == 0;
     auto store_bits = [&](CFAR_GLOBAL uint8_t *dst, const uint32_t(&bits)[(K + 3) / 4]) {
-        if constexpr (MODE == kEdge) {
-            if (k_own0 > 0) {
+        if (!mvec || (BM == kEdge && k_own0 > 0)) {
 #pragma unroll
-                for (int k = 1; k < K; ++k)
-                    if (k >= k_own0) dst[k] = (uint8_t)(bits[k / 4] >> (8 * (k % 4)));
-                return;
-            }
+            for (int k = 0; k < K; ++k)
+                if (k >= k_own0) dst[k] = (uint8_t)(bits[k / 4] >> (8 * (k % 4)));
+            return;
         }
         if constexpr (K == 2) {
             __builtin_nontemporal_store((uint16_t)bits[0], (CFAR_GLOBAL uint16_t *)dst);
@@ -614,7 +629,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         for (int q = 0; q < (K + 3) / 4; ++q) bits[q] = 0u;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const double beta = MODE == kEdge ? beta_lane[MODE == kEdge ? k : 0] : beta_full;
+            const double beta = BM == kEdge ? beta_lane[BM == kEdge ? k : 0] : beta_full;
             const double thr = beta * train_sum_at(k);
             bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
         }
@@ -716,11 +731,11 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         uint32_t so_glead = (uint32_t)(r0 + gr - row_lo) * ldb;
         uint32_t so_lag = 0;
         auto load = [&](T(&b)[NL][K]) {
-            ldk_buf<K, T>(rsx, voff, so_lead, b[0]);
+            ldk_buf<K, T, (MODE & kElem) != 0>(rsx, voff, so_lead, b[0]);
             so_lead += ldb;
             if constexpr (!FULL) {
-                ldk_buf<K, T>(rsx, voff, so_glead, b[1]);
-                ldk_buf<K, T>(rsx, voff, so_lag, b[2]);
+                ldk_buf<K, T, (MODE & kElem) != 0>(rsx, voff, so_glead, b[1]);
+                ldk_buf<K, T, (MODE & kElem) != 0>(rsx, voff, so_lag, b[2]);
                 so_glead += ldb;
                 so_lag += ldb;
             }
@@ -731,7 +746,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             uint32_t so = (uint32_t)(hr - hw) * ldb;  // row r0-hw-1
             for (int i = 0; i < D - 1; ++i) {         // rows r0-hw-1 .. r0+hw-1
                 T v[K];
-                ldk_buf<K, T>(rsx, voff, so, v);
+                ldk_buf<K, T, (MODE & kElem) != 0>(rsx, voff, so, v);
                 T *p = ring_at(sl);
 #pragma unroll
                 for (int k = 0; k < K; ++k) p[k] = v[k];
@@ -858,15 +873,15 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             output_general(r, A[4], PA);
         }
     };
-    if (MODE != kGeneral && !OUT) {
+    if (BM != kGeneral && !OUT) {
         const bool span_ok = (d.vec_ok & 4) != 0;
         const int ring_rows = ring_bytes / (64 * K * (int)sizeof(T));
         const int r_in0 = min(max(hr + 1, ra), rb);
         const int r_in1 = max(min(R - hr, rb), r_in0);
         general_rows(ra, r_in0);
-        if (MODE == kFast && span_ok && 2 * hr + 2 <= ring_rows)
+        if (BM == kFast && span_ok && 2 * hr + 2 <= ring_rows)
             interior(std::true_type(), r_in0, r_in1);
-        else if (MODE == kFast && span_ok && 2 * gr + 2 <= ring_rows)
+        else if (BM == kFast && span_ok && 2 * gr + 2 <= ring_rows)
             interior(std::false_type(), r_in0, r_in1);
         else
             pipelined_fast5(r_in0, r_in1);
@@ -887,25 +902,35 @@ __device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk
 {
     const int F = d.cols, W = 64 * K;
     int cs = strip * d.tw - d.halo_f;
-    const bool vec = (d.vec_ok & 3) == 3 && (d.halo_f % K) == 0;
+    const bool halo_ok = (d.halo_f % K) == 0;
     // The last strip, if its lanes would straddle column F (F not a multiple
     // of K), is right-aligned instead: its last lanes then end on column
     // F + H - 1, so column F falls on a lane boundary, and since its outputs
     // start within the last tw columns it still reaches back H columns
     // before them.  (Earlier strips that reach past F take the general path.)
-    if (vec && strip == d.n_strips - 1 && cs + W > F && F % K != 0 && F + d.halo_f - W >= 0)
+    if (halo_ok && strip == d.n_strips - 1 && cs + W > F && F % K != 0 && F + d.halo_f - W >= 0)
         cs = F + d.halo_f - W;
     const bool inside = cs >= 0 && cs + W <= F;
     // EDGE needs lanes wholly inside or outside: columns 0 and F, where they
     // fall inside the strip, on lane boundaries
     const bool left_ok = cs >= 0 || (cs % K) == 0;
+    const bool edge_ok = F >= K && ((F - cs) % K == 0 || cs + W <= F) && left_ok;
+    // vector loads need 16-byte aligned rows and strip start
+    const bool xvec = (d.vec_ok & 1) != 0 && (cs % (16 / (int)sizeof(T))) == 0;
     T *rg = (T *)ring;
-    if (vec && inside)
-        fused_unit<K, T, kFast, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
-    else if (vec && F >= K && ((F - cs) % K == 0 || cs + W <= F) && left_ok)
-        fused_unit<K, T, kEdge, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
-    else
+    if (halo_ok && inside) {
+        if (xvec)
+            fused_unit<K, T, kFast, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
+        else
+            fused_unit<K, T, kFast | kElem, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
+    } else if (halo_ok && edge_ok) {
+        if (xvec)
+            fused_unit<K, T, kEdge, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
+        else
+            fused_unit<K, T, kEdge | kElem, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
+    } else {
         fused_unit<K, T, kGeneral, OUT>(d, strip, rchunk, strip * d.tw - d.halo_f, qo, qi, rg, ring_bytes, lane);
+    }
 }
 
 #ifndef CFAR_WAVES_16B

@@ -198,3 +198,28 @@ def test_ring_modes_agree(dtype):
             check_full(x_np, spec.window, masks[0], None, None, "tiled", ref=ref)
             for m in masks[1:]:
                 assert np.array_equal(m, masks[0])
+
+
+@pytest.mark.parametrize("cols", [1101, 1102, 1103, 1100])
+def test_padded_rows_and_right_aligned_last_strip(cols):
+    """Maps whose rows are 16-byte aligned (padded leading dimension) but whose
+    width is not a multiple of k: the last strip is right-aligned, its loads
+    and mask stores are not vector-aligned; every plan gives the oracle's
+    mask and the padding of the mask rows stays untouched."""
+    R, ldx = 300, 1112
+    spec = synth.MapSpec(R, cols, "f32", "exp", 1.0, n_targets=10, guard_r=2, guard_f=3, train_r=5, train_f=9,
+                         pfa=1e-4, seed=(22, cols))
+    x_np = synth.generate(spec)
+    big = torch.zeros((R, ldx), dtype=torch.float32, device=DEV)
+    big[:, :cols] = torch.from_numpy(x_np).to(DEV)
+    xv = big[:, :cols]
+    ref = oracle.cfar2d(x_np, *spec.window)
+    for k in (2, 4, 8):
+        for ring in (0, 12288):
+            mbig = torch.full((R, ldx), 7, dtype=torch.uint8, device=DEV)
+            mv = mbig[:, :cols]
+            say("padded", cols, k, ring)
+            C.cfar2d_with_plan(xv, spec.window, k, 64, mask=mv, ring_bytes=ring)
+            torch.cuda.synchronize()
+            check_full(x_np, spec.window, mv.cpu().numpy(), None, None, "tiled", ref=ref)
+            assert (mbig[:, cols:].cpu().numpy() == 7).all()
