@@ -133,8 +133,8 @@ def cpu_baseline(specs, arrays, budget_s=12.0):
 
 def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
     """The serving workload: n_streams simulated drone streams, each emitting
-    frames of its own fixed size at Poisson rate 50 Hz, submitted from pinned
-    host memory to the library's server (continuous batching over 4 HIP
+    frames of its own fixed size at Poisson rate 50 Hz, submitted from
+    page-locked host memory (cfar_host_alloc) to the library's server (continuous batching over 4 HIP
     streams, admission by device memory); latency is frame arrival (its
     scheduled Poisson time) to the mask back in host memory."""
     import threading
@@ -149,10 +149,11 @@ def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
         fr = []
         for j in range(frames_per_stream):
             sp = synth.stream_frame_spec(st, j)
-            fr.append((torch.from_numpy(synth.generate(sp)).pin_memory(), sp.window, sp.cells))
+            x = C.host_empty((sp.rows, sp.cols), torch.float32)   # page-locked (cfar_host_alloc)
+            x.copy_(torch.from_numpy(synth.generate(sp)))
+            fr.append((x, sp.window, sp.cells))
         frames.append(fr)
-        free_masks.append([torch.empty((st["rows"], st["cols"]), dtype=torch.uint8).pin_memory()
-                           for _ in range(masks_per_stream)])
+        free_masks.append([C.host_empty((st["rows"], st["cols"]), torch.uint8) for _ in range(masks_per_stream)])
     # merged Poisson arrival schedule
     arrivals = []
     for k, st in enumerate(streams):
@@ -273,6 +274,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device 3 times (the counter scale of rocprofv3 FETCH_SIZE "
                          "and WRITE_SIZE)")
+    ap.add_argument("--serve-only", action="store_true", help="only the serving run (prints its JSON)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the serving run (16 Poisson streams at 50 Hz); 0 skips it")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -305,6 +307,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}), flush=True)
         return
     C.lib()
+    if args.serve_only:
+        print(json.dumps(serve_bench(args.serve_seconds)), flush=True)
+        return
 
     specs, desc = build_workload(args.workload)
     log("generating %d maps" % len(specs))

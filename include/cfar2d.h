@@ -221,6 +221,14 @@ typedef struct {
     int32_t inflight_frames, queued_frames;
 } cfar_server_stats;
 
+/* Page-locked host memory for frames and masks submitted with x_on_host = 1
+ * (hipHostMalloc): copies from and to it run at full link speed and overlap
+ * with other work.  *out is host memory of `bytes` bytes, freed with
+ * cfar_host_free.  Errors: CFAR_EINVAL (bytes == 0 or out NULL),
+ * CFAR_EDEVICE (allocation failed). */
+int cfar_host_alloc(size_t bytes, void **out);
+int cfar_host_free(void *p);
+
 /* Create a server: allocates its device pool (device_budget_bytes, clamped
  * to the free device memory) and starts its scheduler thread. */
 int cfar_server_create(const cfar_server_opts *opts, cfar_server **out);

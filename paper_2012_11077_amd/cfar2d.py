@@ -105,12 +105,14 @@ def lib():
         L.cfar_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
         L.cfar_server_shutdown.argtypes = [_vp, _i32]
         L.cfar_server_destroy.argtypes = [_vp]
+        L.cfar_host_alloc.argtypes = [_sz, ctypes.POINTER(_vp)]
+        L.cfar_host_free.argtypes = [_vp]
         L.cfar_timing_enable.argtypes = [_i32]
         L.cfar_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
         for name in ("sat2d", "cfar2d", "cfar2d_batched", "cfar_plan_for", "cfar_plan_load",
                      "cfar2d_with_plan", "cfar_timing_enable", "cfar_timing_read", "cfar_server_create",
                      "cfar_submit", "cfar_poll", "cfar_server_stats_get", "cfar_server_shutdown",
-                     "cfar_server_destroy"):
+                     "cfar_server_destroy", "cfar_host_alloc", "cfar_host_free"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         table = os.environ.get("CFAR2D_PLAN_TABLE")
@@ -338,6 +340,25 @@ def timing_read() -> float:
 
 def plan_load(path: Optional[str]) -> None:
     _check(lib().cfar_plan_load(path.encode() if path else None))
+
+
+def host_empty(shape, dtype=torch.float32) -> torch.Tensor:
+    """A CPU tensor in page-locked memory from cfar_host_alloc (full-speed
+    copies for frames submitted from host memory); freed when the tensor and
+    every view of it are gone."""
+    import weakref
+    import numpy as np
+    np_dtype = {torch.float32: np.float32, torch.float64: np.float64, torch.uint8: np.uint8}[dtype]
+    n = 1
+    for d in shape:
+        n *= int(d)
+    nbytes = max(1, n * np.dtype(np_dtype).itemsize)
+    p = ctypes.c_void_p()
+    _check(lib().cfar_host_alloc(nbytes, ctypes.byref(p)))
+    buf = (ctypes.c_char * nbytes).from_address(p.value)
+    arr = np.frombuffer(buf, dtype=np_dtype, count=n).reshape(shape)
+    weakref.finalize(buf, lib().cfar_host_free, ctypes.c_void_p(p.value))
+    return torch.from_numpy(arr)
 
 
 class Server:

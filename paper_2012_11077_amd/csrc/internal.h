@@ -58,7 +58,7 @@ struct FusedArgs {
 // (header + descriptors + unit tables) with one host-to-device copy; the
 // threshold tables that follow are filled on the device.
 struct BatchHeader {
-    uint32_t counter[16];  // one work counter per kernel class (k, dtype, outputs)
+    uint32_t counter[16];  // one work counter per kernel class (k set, dtype, outputs, alignment)
     uint32_t n_maps;
     uint32_t total_units;
     uint32_t pad[46];
@@ -113,13 +113,14 @@ hipError_t launch_lut(const MapDesc *descs, const MapDesc &single, int n, uint32
 hipError_t launch_stencil_plain(const MapDesc &d, const double *sat, hipStream_t stream);
 
 // Persistent TILED kernel over all work units in `args`.  One kernel per
-// (k set, dtype, out): kset 24 serves maps planned with k = 2 or 4 (one
+// (k set, dtype, out, ua): kset 24 serves maps planned with k = 2 or 4 (one
 // launch for both), kset 8 maps with k = 8; out = maps may carry the
-// optional training-sum / threshold outputs.
-hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, hipStream_t stream);
+// optional training-sum / threshold outputs; ua = the maps' rows are not
+// 16-byte aligned (element loads).
+hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, bool ua, hipStream_t stream);
 
 // Number of persistent workgroups of that kernel that fit the device.
-int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes);
+int fused_resident_blocks(int kset, int dtype, bool out, bool ua, int ring_bytes);
 
 constexpr int kFusedThreads = 64;  // one wave per workgroup: LDS is sized per wave
 constexpr int kMaxK = 8;

@@ -440,7 +440,7 @@ struct OffsetRead {
 template <int K, typename T>
 constexpr int prefetch_rows() { return K * sizeof(T) >= 32 ? 2 : CFAR_PREFETCH_ROWS; }
 #ifndef CFAR_PREFETCH_ROWS_FULL
-#define CFAR_PREFETCH_ROWS_FULL 6
+#define CFAR_PREFETCH_ROWS_FULL 3
 #endif
 template <int K, typename T>
 constexpr int prefetch_rows_full() { return K * sizeof(T) >= 32 ? 3 : CFAR_PREFETCH_ROWS_FULL; }
@@ -694,8 +694,9 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         }
     };
 
-    // Interior rows of FAST units without the optional outputs (EDGE units
-    // take the five-load loop below): every row of both windows inside the map, so the accumulators take plain adds and
+    // Interior rows of FAST and EDGE units without the optional outputs
+    // (EDGE: lanes outside the map load column 0, weighed by zero): every
+    // row of both windows inside the map, so the accumulators take plain adds and
     // subtractions.  Rows come through a buffer resource over the rows this
     // loop touches, with wave-uniform row offsets that advance one row per
     // step and PD rows in flight, and through a per-wave LDS ring (slot of
@@ -710,7 +711,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
     auto interior = [&](auto full_tag, int r0, int r1) {
         constexpr bool FULL = decltype(full_tag)::value;
         if (r0 >= r1) return;
-        constexpr int PD = FULL ? prefetch_rows_full<K, T>() : prefetch_rows<K, T>();
+        constexpr int PD = (MODE & kElem) ? 2 : FULL ? prefetch_rows_full<K, T>() : prefetch_rows<K, T>();
         constexpr int NL = FULL ? 1 : 3;  // global loads per row
         const int D = FULL ? 2 * hr + 2 : 2 * gr + 2;
         const int hw = FULL ? hr : gr;  // half-width of the rows the ring serves
@@ -726,7 +727,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
                                                                (uint32_t)F * (uint32_t)sizeof(T));
         const __amdgpu_buffer_rsrc_t rsx = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(uintptr_t)(((uint64_t)base_hi << 32) | base_lo), (short)0, extent, kBufferFlags);
-        const uint32_t voff = (uint32_t)c_lane * (uint32_t)sizeof(T);
+        const uint32_t voff = lane_outside ? 0u : (uint32_t)c_lane * (uint32_t)sizeof(T);  // EDGE: column 0
         uint32_t so_lead = (uint32_t)(r0 + hr - row_lo) * ldb;
         uint32_t so_glead = (uint32_t)(r0 + gr - row_lo) * ldb;
         uint32_t so_lag = 0;
@@ -801,8 +802,13 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                Co[k] = (Co[k] + (double)b[0][k]) - (double)la[k];
-                Ci[k] = (Ci[k] + (double)gle[k]) - (double)gla[k];
+                if constexpr (BM == kEdge) {  // lanes outside the map weigh zero
+                    Co[k] = __builtin_fma(-lane_w, (double)la[k], __builtin_fma(lane_w, (double)b[0][k], Co[k]));
+                    Ci[k] = __builtin_fma(-lane_w, (double)gla[k], __builtin_fma(lane_w, (double)gle[k], Ci[k]));
+                } else {
+                    Co[k] = (Co[k] + (double)b[0][k]) - (double)la[k];
+                    Ci[k] = (Ci[k] + (double)gle[k]) - (double)gla[k];
+                }
             }
             publish();
             uint32_t bits[(K + 3) / 4];
@@ -879,9 +885,9 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         const int r_in0 = min(max(hr + 1, ra), rb);
         const int r_in1 = max(min(R - hr, rb), r_in0);
         general_rows(ra, r_in0);
-        if (BM == kFast && span_ok && 2 * hr + 2 <= ring_rows)
+        if (BM == kFast && span_ok && 2 * hr + 2 <= ring_rows)  // (EDGE: guard ring only, for registers)
             interior(std::true_type(), r_in0, r_in1);
-        else if (BM == kFast && span_ok && 2 * gr + 2 <= ring_rows)
+        else if (span_ok && 2 * gr + 2 <= ring_rows)
             interior(std::false_type(), r_in0, r_in1);
         else
             pipelined_fast5(r_in0, r_in1);
@@ -896,7 +902,9 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_
 // One wave per workgroup; dynamic LDS per wave: the two prefix rows
 // (2*K*64 doubles), then the ring of args.ring_rows rows of 64*K values.
 // Mode of one work unit (see fused_unit) and its run.
-template <int K, typename T, bool OUT>
+// UA: the map's rows are not 16-byte aligned (its own kernel, so that the
+// element-load variants do not crowd the register allocation of the others).
+template <int K, typename T, bool OUT, bool UA>
 __device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk, double *qo, double *qi, void *ring,
                                          int ring_bytes, int lane)
 {
@@ -918,16 +926,10 @@ __device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk
     // vector loads need 16-byte aligned rows and strip start
     const bool xvec = (d.vec_ok & 1) != 0 && (cs % (16 / (int)sizeof(T))) == 0;
     T *rg = (T *)ring;
-    if (halo_ok && inside) {
-        if (xvec)
-            fused_unit<K, T, kFast, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
-        else
-            fused_unit<K, T, kFast | kElem, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
-    } else if (halo_ok && edge_ok) {
-        if (xvec)
-            fused_unit<K, T, kEdge, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
-        else
-            fused_unit<K, T, kEdge | kElem, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
+    if (halo_ok && inside && (UA || xvec)) {
+        fused_unit<K, T, UA ? (kFast | kElem) : kFast, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
+    } else if (halo_ok && edge_ok && (UA || xvec)) {
+        fused_unit<K, T, UA ? (kEdge | kElem) : kEdge, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
     } else {
         fused_unit<K, T, kGeneral, OUT>(d, strip, rchunk, strip * d.tw - d.halo_f, qo, qi, rg, ring_bytes, lane);
     }
@@ -938,7 +940,7 @@ __device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk
 #endif
 // Waves per SIMD the register allocation aims at, by bytes per lane and row
 // (the LDS of one wave is small, so registers set the occupancy).
-template <int KS, typename T, bool OUT>
+template <int KS, typename T, bool OUT, bool UA>
 constexpr int fused_waves()
 {
     return KS == 8 ? 1 : sizeof(T) == 4 ? (OUT ? 2 : CFAR_WAVES_16B) : (OUT ? 1 : 2);
@@ -947,8 +949,8 @@ constexpr int fused_waves()
 // One wave per workgroup; dynamic LDS per wave: the two prefix rows
 // (2*kmax*64 doubles), then the ring of args.ring_bytes.  KS = 24: each
 // unit runs with its map's k (2 or 4); KS = 8: k = 8.
-template <int KS, typename T, bool OUT>
-__global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(fused_waves<KS, T, OUT>())))
+template <int KS, typename T, bool OUT, bool UA>
+__global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(fused_waves<KS, T, OUT, UA>())))
 fused_kernel(FusedArgs args)
 {
     constexpr int KM = KS == 8 ? 8 : 4;
@@ -979,41 +981,45 @@ fused_kernel(FusedArgs args)
         const int strip = (int)(local % (uint32_t)d.n_strips);
         const int rchunk = (int)(local / (uint32_t)d.n_strips);
         if constexpr (KS == 8) {
-            run_unit<8, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
+            run_unit<8, T, OUT, UA>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
         } else {
             if (d.k_cols == 2)
-                run_unit<2, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
+                run_unit<2, T, OUT, UA>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
             else
-                run_unit<4, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
+                run_unit<4, T, OUT, UA>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
         }
     }
 }
 
-#define CFAR_FUSED_VARIANTS(X_)                                                                              \
-    X_(24, float, false) X_(24, float, true) X_(24, double, false) X_(24, double, true) X_(8, float, false) \
-    X_(8, float, true) X_(8, double, false) X_(8, double, true)
+#define CFAR_FUSED_VARIANTS(X_)                                                                        \
+    X_(24, float, false, false) X_(24, float, true, false) X_(24, double, false, false)                  \
+    X_(24, double, true, false) X_(8, float, false, false) X_(8, float, true, false)                    \
+    X_(8, double, false, false) X_(8, double, true, false) X_(24, float, false, true)                    \
+    X_(24, float, true, true) X_(24, double, false, true) X_(24, double, true, true)                    \
+    X_(8, float, false, true) X_(8, float, true, true) X_(8, double, false, true) X_(8, double, true, true)
 
-static const void *fused_fn(int kset, int dtype, bool out)
+static const void *fused_fn(int kset, int dtype, bool out, bool ua)
 {
-#define CFAR_PICK(K_, T_, O_) \
-    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) return (const void *)fused_kernel<K_, T_, O_>;
+#define CFAR_PICK(K_, T_, O_, U_)                                                    \
+    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_ && ua == U_) \
+        return (const void *)fused_kernel<K_, T_, O_, U_>;
     CFAR_FUSED_VARIANTS(CFAR_PICK)
 #undef CFAR_PICK
     return nullptr;
 }
 
-int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes)
+int fused_resident_blocks(int kset, int dtype, bool out, bool ua, int ring_bytes)
 {
     // cache: device x kernel x ring size (in 512-byte steps)
     constexpr int kSteps = 129;
-    static int cached[16][8][kSteps] = {{{0}}};
+    static int cached[16][16][kSteps] = {{{0}}};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
-    const int slot = ((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0);
+    const int slot = (((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0)) * 2 + (ua ? 1 : 0);
     const int step = ring_bytes % 512 == 0 && ring_bytes / 512 < kSteps ? ring_bytes / 512 : -1;
     int *c = dev < 16 && step >= 0 ? &cached[dev][slot][step] : nullptr;
     if (c && *c > 0) return *c;
-    const void *fn = fused_fn(kset, dtype, out);
+    const void *fn = fused_fn(kset, dtype, out, ua);
     int per_cu = 0, cus = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFusedThreads,
                                                             fused_lds_bytes(kset, ring_bytes)) != hipSuccess ||
@@ -1026,17 +1032,17 @@ int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes)
     return per_cu * cus;
 }
 
-hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, hipStream_t stream)
+hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, bool ua, hipStream_t stream)
 {
-    const int resident = fused_resident_blocks(kset, dtype, out, args.ring_bytes);
+    const int resident = fused_resident_blocks(kset, dtype, out, ua, args.ring_bytes);
     uint32_t blocks = args.total_units;
     if (blocks > (uint32_t)resident) blocks = (uint32_t)resident;
     if (blocks == 0) blocks = 1;
     const size_t lds = fused_lds_bytes(kset, args.ring_bytes);
-#define CFAR_LAUNCH(K_, T_, O_)                                                                                \
-    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) {                                       \
-        hipLaunchKernelGGL((fused_kernel<K_, T_, O_>), dim3(blocks), dim3(kFusedThreads), lds, stream, args); \
-        return hipGetLastError();                                                                              \
+#define CFAR_LAUNCH(K_, T_, O_, U_)                                                                                \
+    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_ && ua == U_) {                               \
+        hipLaunchKernelGGL((fused_kernel<K_, T_, O_, U_>), dim3(blocks), dim3(kFusedThreads), lds, stream, args); \
+        return hipGetLastError();                                                                                  \
     }
     CFAR_FUSED_VARIANTS(CFAR_LAUNCH)
 #undef CFAR_LAUNCH

@@ -209,8 +209,11 @@ int launch(cfar_server *s, Batch &b)
             char *dx = s->pool_base + f.off_x;
             uint8_t *dm = (uint8_t *)(s->pool_base + f.off_m);
             const size_t es = frame_es(m);
-            hipError_t e = hipMemcpy2DAsync(dx, (size_t)m.cols * es, m.x, (size_t)m.ld * es, (size_t)m.cols * es,
-                                            (size_t)m.rows, hipMemcpyHostToDevice, st);
+            // contiguous frames as one copy (a 2D copy may go row by row)
+            hipError_t e = m.ld == m.cols
+                               ? hipMemcpyAsync(dx, m.x, (size_t)m.rows * (size_t)m.cols * es, hipMemcpyHostToDevice, st)
+                               : hipMemcpy2DAsync(dx, (size_t)m.cols * es, m.x, (size_t)m.ld * es,
+                                                  (size_t)m.cols * es, (size_t)m.rows, hipMemcpyHostToDevice, st);
             if (e != hipSuccess) return hip_error(e, "hipMemcpy2DAsync(frame in)");
             m.x = dx;
             m.ld = m.cols;
@@ -225,8 +228,11 @@ int launch(cfar_server *s, Batch &b)
     for (size_t i = 0; i < b.frames.size(); ++i) {
         const Frame &f = b.frames[i];
         if (!f.on_host) continue;
-        hipError_t e = hipMemcpy2DAsync(f.map.mask, (size_t)f.map.ld_mask, maps[i].mask, (size_t)f.map.cols,
-                                        (size_t)f.map.cols, (size_t)f.map.rows, hipMemcpyDeviceToHost, st);
+        hipError_t e = f.map.ld_mask == f.map.cols
+                           ? hipMemcpyAsync(f.map.mask, maps[i].mask, (size_t)f.map.rows * (size_t)f.map.cols,
+                                            hipMemcpyDeviceToHost, st)
+                           : hipMemcpy2DAsync(f.map.mask, (size_t)f.map.ld_mask, maps[i].mask, (size_t)f.map.cols,
+                                              (size_t)f.map.cols, (size_t)f.map.rows, hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) return hip_error(e, "hipMemcpy2DAsync(mask out)");
     }
     hipError_t e = hipEventRecord(b.done, st);
@@ -390,6 +396,23 @@ void scheduler(cfar_server *s)
 using namespace cfar;
 
 extern "C" {
+
+int cfar_host_alloc(size_t bytes, void **out)
+{
+    if (!out || bytes == 0) return set_error(CFAR_EINVAL, "bytes is 0 or out is NULL");
+    *out = nullptr;
+    hipError_t e = hipHostMalloc(out, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return hip_error(e, "hipHostMalloc");
+    return CFAR_OK;
+}
+
+int cfar_host_free(void *p)
+{
+    if (!p) return CFAR_OK;
+    hipError_t e = hipHostFree(p);
+    if (e != hipSuccess) return hip_error(e, "hipHostFree");
+    return CFAR_OK;
+}
 
 int cfar_server_create(const cfar_server_opts *opts, cfar_server **out)
 {

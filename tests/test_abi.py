@@ -78,7 +78,17 @@ def test_sat2d_sizes(L):
     assert L.sat2d_workspace_bytes(1000, 1000, C.PLAIN) > 0
 
 
-def test_planner_follows_the_cost_model(L):
+@pytest.fixture
+def builtin_model(L):
+    """The built-in cost model for the test; the package's plan table (if
+    any) is loaded again afterwards."""
+    C.plan_load(None)
+    yield
+    if os.path.exists(C.DEFAULT_PLAN_TABLE) and os.environ.get("CFAR2D_PLAN_TABLE") is None:
+        C.plan_load(C.DEFAULT_PLAN_TABLE)
+
+
+def test_planner_follows_the_cost_model(L, builtin_model):
     def plan(rows, cols, win):
         m = _map(rows, cols, win=win)
         p = C.Plan()
@@ -91,7 +101,7 @@ def test_planner_follows_the_cost_model(L):
     assert rs == 50 and ring == -1                                # short map: one row chunk
 
 
-def test_plan_table_rules(L, tmp_path):
+def test_plan_table_rules(L, tmp_path, builtin_model):
     good = tmp_path / "plans.txt"
     good.write_text("# dtype cols rows hf hr k rs [ring]\n"
                     "f32 0 1000 0 100000 0 300 0 300 8 32 4096\n"
@@ -114,6 +124,11 @@ def test_plan_table_rules(L, tmp_path):
             C.plan_load(str(bad))
     finally:
         C.plan_load(None)
+
+
+def test_package_plan_table_parses(L):
+    if os.path.exists(C.DEFAULT_PLAN_TABLE):
+        C.plan_load(C.DEFAULT_PLAN_TABLE)
 
 
 def test_invalid_plans_are_rejected(L):

@@ -40,7 +40,7 @@ def _drain(srv, tickets, timeout_s=60.0):
 
 
 def test_alone_equals_in_mix():
-    """Host (pinned) and device frames of many sizes, windows and Pfa,
+    """Host (page-locked) and device frames of many sizes, windows and Pfa,
     submitted together over several HIP streams: every mask equals the one
     the frame gets alone, and matches the oracle."""
     specs, xs = _frames(40, seed=31)
@@ -49,7 +49,12 @@ def test_alone_equals_in_mix():
                   queue_depth=64, max_batch_frames=6) as srv:
         keep, tickets = [], {}
         for k, (s, x) in enumerate(zip(specs, xs)):
-            if k % 2 == 0:   # host frame, pinned
+            if k % 4 == 0:   # host frame, page-locked by the library
+                xh = C.host_empty(x.shape, torch.from_numpy(x).dtype)
+                xh.copy_(torch.from_numpy(x))
+                mh = C.host_empty(x.shape, torch.uint8)
+                mh.fill_(7)
+            elif k % 4 == 2:  # host frame, torch pinned memory
                 xh = torch.from_numpy(x).pin_memory()
                 mh = torch.full(x.shape, 7, dtype=torch.uint8).pin_memory()
             else:            # device frame
