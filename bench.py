@@ -63,23 +63,28 @@ def measured_traffic():
 
 
 def _counter_per_dispatch(path, counter, kernel_substr, reduce="mean"):
-    """Mean (or max) value of a rocprofv3 counter per dispatch of the kernels
-    whose name contains kernel_substr, from the sqlite database(s) under path."""
+    """A rocprofv3 counter over the dispatches of the kernels whose name
+    contains kernel_substr (sqlite database(s) under path): reduce "max" =
+    the largest dispatch, "mean" = the mean per launch group, where a group
+    holds one dispatch of each distinct kernel (the kernel classes of one
+    batched launch run concurrently).  Returns (value, dispatches)."""
     import glob
     import sqlite3
-    vals = {}
+    vals, names = {}, set()
     for db in glob.glob(os.path.join(path, "**", "*.db"), recursive=True):
         c = sqlite3.connect(db)
         for name, disp, v in c.execute("select kernel_name, dispatch_id, value from counters_collection "
                                        "where counter_name = ?", (counter,)):
             if kernel_substr in name:
                 vals[(db, disp)] = vals.get((db, disp), 0.0) + float(v)
+                names.add(name)
         c.close()
     if not vals:
         raise SystemExit("no %s samples for %r under %s" % (counter, kernel_substr, path))
     if reduce == "max":
         return max(vals.values()), len(vals)
-    return sum(vals.values()) / len(vals), len(vals)
+    groups = len(vals) / max(1, len(names))
+    return sum(vals.values()) / groups, len(vals)
 
 
 def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workload, command):
@@ -95,7 +100,7 @@ def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workloa
     fk, n1 = _counter_per_dispatch(fetch_dir, "FETCH_SIZE", "fused_kernel")
     wk, n2 = _counter_per_dispatch(write_dir, "WRITE_SIZE", "fused_kernel")
     t = {"kernel": "fused_kernel", "workload": workload, "kernel_sha": kernel_source_sha(),
-         "fetch_kib_per_dispatch": round(fk, 1), "write_kib_per_dispatch": round(wk, 1),
+         "fetch_kib_per_launch": round(fk, 1), "write_kib_per_launch": round(wk, 1),
          "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
          "bytes_per_launch": int(fk * 1024.0 * f_scale + wk * 1024.0 * w_scale),
          "dispatches": [n1, n2], "command": command}
