@@ -313,11 +313,28 @@ static bool has_outputs(const cfar_map *m) { return m->train_sum != nullptr || m
 
 static uint64_t units_of(const Plan &p) { return (uint64_t)p.n_strips * (uint64_t)p.n_rchunks; }
 
-// LDS ring bytes map m needs under its plan's budget.
+// LDS one workgroup may use on the current device (queried once).
+static int max_lds_per_block()
+{
+    static int v = 0;
+    if (v == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        v = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+             prop.sharedMemPerBlock > 0)
+                ? (int)prop.sharedMemPerBlock
+                : 65536;
+    }
+    return v;
+}
+
+// LDS ring bytes map m needs under its plan's budget (and what one
+// workgroup can hold besides the prefix rows).
 static int map_ring_bytes(const cfar_map *m, const Plan &p)
 {
     const int hr = m->win.guard_r + m->win.train_r;
-    return ring_bytes_needed(p.k, m->dtype, hr, m->win.guard_r, p.ring_bytes);
+    const int room = max_lds_per_block() - (int)fused_lds_bytes(kset_of(p.k), 0);
+    return ring_bytes_needed(p.k, m->dtype, hr, m->win.guard_r, std::min(p.ring_bytes, std::max(room, 0)));
 }
 
 // ---------------------------------------------------------------------------

@@ -178,7 +178,8 @@ def test_plans_give_the_same_answer():
 def test_ring_modes_agree(dtype):
     """The interior loop's three row sources (every row from the LDS ring,
     guard rows from the ring, no ring) give the same mask, bit for bit, and
-    match the oracle; windows chosen so each mode is taken for each k."""
+    match the oracle; windows and ring budgets chosen so each mode is taken
+    for each k."""
     for (g, t, cols) in [(1, 2, 1100), (2, 5, 1102), (4, 12, 1101), (2, 3, 1024)]:
         # cols % 4 == 0, % 2 only, odd, % 8 == 0: border strips take the EDGE
         # mode or the general one
@@ -189,7 +190,7 @@ def test_ring_modes_agree(dtype):
         ref = oracle.cfar2d(x_np, *spec.window)
         for k in (2, 4, 8):
             masks = []
-            for ring in (0, 2 * 1024, 8 * 1024, 65536):
+            for ring in (0, 2 * 1024, 8 * 1024, 24 * 1024, 65536):
                 mask = torch.empty(x.shape, dtype=torch.uint8, device=DEV)
                 say("ring", dtype, g, t, k, ring)
                 C.cfar2d_with_plan(x, spec.window, k, 64, mask=mask, ring_bytes=ring)
