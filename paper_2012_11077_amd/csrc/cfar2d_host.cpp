@@ -246,7 +246,7 @@ static MapDesc make_desc(const cfar_map *m, const Plan *p, double *lut)
         const bool m_vec = ((uintptr_t)m->mask % 4 == 0) && (m->ld_mask % 4 == 0);
         // bit 4: the rows one work unit reads span fewer than 2^31 bytes, so
         // the interior loop can address them through one buffer resource
-        const double span = ((double)p->rs + 2.0 * d.hr + 2.0) * (double)m->ld * (double)es;
+        const double span = ((double)p->rs + 2.0 * d.hr + 2.0) * std::max((double)m->ld * (double)es, (double)m->ld_mask);
         d.vec_ok = (x_vec ? 1 : 0) | (m_vec ? 2 : 0) | (span < 2147483647.0 ? 4 : 0);
     }
     return d;

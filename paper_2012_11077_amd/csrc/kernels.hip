@@ -627,11 +627,32 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
     auto decide_fast = [&](const T(&xcut)[K], uint32_t(&bits)[(K + 3) / 4]) {
 #pragma unroll
         for (int q = 0; q < (K + 3) / 4; ++q) bits[q] = 0u;
+        if constexpr (MODE == kFast || MODE == kEdge) {
+            // every corner read is issued before the first is used: the LDS
+            // round trips overlap instead of following one another (the
+            // element-load variants keep the plain order: registers run short)
+            double oh[K], ol[K], ih[K], il[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double beta = BM == kEdge ? beta_lane[BM == kEdge ? k : 0] : beta_full;
-            const double thr = beta * train_sum_at(k);
-            bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
+            for (int k = 0; k < K; ++k) {
+                oh[k] = rd_oh.get(qo, k);
+                ol[k] = rd_ol.get(qo, k);
+                ih[k] = rd_ih.get(qi, k);
+                il[k] = rd_il.get(qi, k);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double beta = BM == kEdge ? beta_lane[BM == kEdge ? k : 0] : beta_full;
+                const double thr = beta * ((oh[k] - ol[k]) - (ih[k] - il[k]));
+                bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double beta = BM == kEdge ? beta_lane[BM == kEdge ? k : 0] : beta_full;
+                const double thr = beta * train_sum_at(k);
+                bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
+            }
         }
     };
     auto output_fast = [&](int r, const T(&xcut)[K]) {
@@ -759,6 +780,20 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         int s_w = (r0 + hw) % D, s_c = r0 % D, s_g = (r0 + gr) % D, s_gl = (r0 - gr - 1 + D) % D;
         CFAR_GLOBAL uint8_t *mptr = gbl_w(d.mask) + (int64_t)r0 * d.ld_mask + c_lane;  // stored only where lane_any_out
         const int64_t mstep = d.ld_mask;
+        // FAST: the mask rows r0..r1-1 through a buffer resource too; a lane
+        // without output columns stores past its end, where the store is
+        // dropped, so the store needs no branch (and no alignment: the
+        // packed store of a lane may straddle dwords)
+        const uint64_t mbase = (uint64_t)(uintptr_t)(d.mask + (int64_t)r0 * d.ld_mask);
+        const uint32_t mb_lo = __builtin_amdgcn_readfirstlane((uint32_t)mbase);
+        const uint32_t mb_hi = __builtin_amdgcn_readfirstlane((uint32_t)(mbase >> 32));
+        const int mext = (int)__builtin_amdgcn_readfirstlane((uint32_t)(r1 - 1 - r0) * (uint32_t)d.ld_mask +
+                                                             (uint32_t)F);
+        const __amdgpu_buffer_rsrc_t rsm = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(uintptr_t)(((uint64_t)mb_hi << 32) | mb_lo), (short)0, mext, kBufferFlags);
+        const uint32_t moff = lane_any_out ? (uint32_t)c_lane : 0x80000000u;
+        const uint32_t mstep_u = __builtin_amdgcn_readfirstlane((uint32_t)d.ld_mask);
+        uint32_t so_m = 0;
         auto next = [&](int v) { return v + 1 == D ? 0 : v + 1; };
         auto step = [&](const T(&b)[NL][K]) {
             T gle[K], gla[K], la[K], xc[K];
@@ -813,8 +848,21 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             publish();
             uint32_t bits[(K + 3) / 4];
             decide_fast(xc, bits);
-            if (lane_any_out) store_bits(mptr, bits);
-            mptr += mstep;
+            if constexpr (BM == kFast) {
+                if constexpr (K == 2) {
+                    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)bits[0], rsm, moff, so_m, 0);
+                } else if constexpr (K == 4) {
+                    __builtin_amdgcn_raw_buffer_store_b32(bits[0], rsm, moff, so_m, 0);
+                } else {
+                    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                    const u32x2 w = {bits[0], bits[1]};
+                    __builtin_amdgcn_raw_buffer_store_b64(w, rsm, moff, so_m, 0);
+                }
+                so_m += mstep_u;
+            } else {
+                if (lane_any_out) store_bits(mptr, bits);
+                mptr += mstep;
+            }
         };
         T buf[PD][NL][K];
         int r = r0;

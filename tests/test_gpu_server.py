@@ -85,15 +85,19 @@ def test_alone_equals_in_mix():
 def test_backpressure_and_small_budget():
     """A tiny queue gives CFAR_EAGAIN; a budget that holds only a few frames
     admits them as memory frees up; every frame still completes."""
-    specs, xs = _frames(30, seed=32, rows=(200, 300), cols=(200, 300))
+    # frames of about 5 MB (input and mask), a budget of 16 MB: at most three
+    # on the device at once, each taking its copies' time (about 0.1 ms)
+    specs, xs = _frames(30, seed=32, rows=(900, 1100), cols=(900, 1100))
     ref = [_alone(x, s.window) for x, s in zip(xs, specs)]
-    with C.Server(device_budget_bytes=2 << 20, max_inflight_frames=4, n_hip_streams=2,
+    budget = 16 << 20
+    with C.Server(device_budget_bytes=budget, max_inflight_frames=4, n_hip_streams=2,
                   queue_depth=3, max_batch_frames=2) as srv:
-        keep, tickets, eagain = [], {}, 0
-        for k, (s, x) in enumerate(zip(specs, xs)):
-            xh = torch.from_numpy(x).pin_memory()
-            mh = torch.zeros(x.shape, dtype=torch.uint8).pin_memory()
-            keep.append((xh, mh))
+        # every frame is page-locked before the first submit, so the submits
+        # come faster than the device completes frames
+        keep = [(torch.from_numpy(x).pin_memory(), torch.zeros(x.shape, dtype=torch.uint8).pin_memory())
+                for x in xs]
+        tickets, eagain = {}, 0
+        for k, (s, (xh, mh)) in enumerate(zip(specs, keep)):
             while True:
                 t = srv.submit(xh, s.window, mh, tag=k)
                 if t is not None:
@@ -104,7 +108,7 @@ def test_backpressure_and_small_budget():
         got = _drain(srv, tickets)
         st = srv.stats()
     assert eagain > 0
-    assert st.device_bytes_peak <= 2 << 20
+    assert st.device_bytes_peak <= budget
     for t, c in got.items():
         assert c.status == C.CFAR_OK
         assert np.array_equal(keep[tickets[t]][1].numpy(), ref[tickets[t]])
