@@ -17,7 +17,11 @@ context:
    times the whole workload with every candidate rule for that family in
    front of the rules fixed so far (library kernel timing, median of
    repetitions), keeping the fastest;
-3. the fixed rules are written as a plan table (the format cfar_plan_load
+3. the batch's rules are kept only if, on a held-out batch (a third seed),
+   they beat the cost model (with the large-map rules in front of both):
+   coordinate descent on one noisy batch can fit that batch and nothing
+   else;
+4. the fixed rules are written as a plan table (the format cfar_plan_load
    reads: ``dtype cols_lo cols_hi rows_lo rows_hi hf_lo hf_hi hr_lo hr_hi k
    rows_per_unit ring_bytes``).  Maps that match no rule keep the cost model.
 """
@@ -143,6 +147,7 @@ def main():
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "plan_table.txt"))
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--seed", type=int, default=103, help="seed of the tuning batch (the benchmark uses 3)")
+    ap.add_argument("--val-seed", type=int, default=203, help="seed of the held-out batch")
     args = ap.parse_args()
     import torch
     if not torch.cuda.is_available():
@@ -162,7 +167,22 @@ def main():
             del w
             torch.cuda.empty_cache()
         w = Workload(synth.config3_specs(seed=args.seed), args.seed, dev)
-        rules = tune(w, rules, probe, args.reps, log) + rules
+        batch_rules = tune(w, rules, probe, args.reps, log)
+        del w
+        torch.cuda.empty_cache()
+        v = Workload(synth.config3_specs(seed=args.val_seed), args.val_seed, dev)
+
+        def held_out(rs):
+            with open(probe, "w") as f:
+                f.write("\n".join(rs) + "\n")
+            C.plan_load(probe)
+            return v.time(args.reps)
+        t_tuned, t_model = held_out(batch_rules + rules), held_out(rules)
+        keep = t_tuned < t_model
+        log({"held_out_seed": args.val_seed, "tuned_ms": round(t_tuned, 4), "builtin_model_ms": round(t_model, 4),
+             "batch_rules_kept": keep})
+        if keep:
+            rules = batch_rules + rules
     C.plan_load(None)
     with open(args.out, "w") as f:
         f.write("# Tile plans chosen by paper_2012_11077_amd/autotune.py (in-context coordinate descent) on %s, %s\n"
