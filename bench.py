@@ -36,7 +36,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "CA-CFAR cells/s & % HBM peak, chosen vs plain form at equal mask; p99 latency"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_kernel_uneven_batch_traffic.json")
+# rocprofv3 counter summaries of the fused kernel, per workload
+TRAFFIC_FILES = {"batched": os.path.join(ROOT, "profiles", "fused_kernel_uneven_batch_traffic.json"),
+                 "precision": os.path.join(ROOT, "profiles", "fused_kernel_16k_f32_map_traffic.json")}
 
 
 def log(*a):
@@ -49,11 +51,14 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter runs, if they were taken on the current kernel source."""
+    counter runs of the workload, if they were taken on the current kernel
+    source."""
+    if workload not in TRAFFIC_FILES:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[workload]) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -104,7 +109,7 @@ def record_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, workloa
          "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
          "bytes_per_launch": int(fk * 1024.0 * f_scale + wk * 1024.0 * w_scale),
          "dispatches": [n1, n2], "command": command}
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(TRAFFIC_FILES[workload], "w") as f:
         json.dump(t, f, indent=1)
     print(json.dumps(t), flush=True)
 
@@ -286,6 +291,8 @@ def main():
                     help="write the traffic file from rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
     if args.record_traffic:
+        if args.workload not in TRAFFIC_FILES:
+            raise SystemExit("traffic is recorded for the workloads %s" % sorted(TRAFFIC_FILES))
         record_traffic(*args.record_traffic, workload=args.workload,
                        command="rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --profile-only "
                                "--workload %s; copy scale from bench.py --copy-probe" % args.workload)
@@ -372,7 +379,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "fused_kernel", "kernel_ms": round(kernel_ms, 4),
             "alg_bytes_per_cell": round(alg_bytes / cells, 3)}
-    tr = measured_traffic()
+    tr = measured_traffic(args.workload)
     if tr and tr.get("workload") == args.workload:
         roof["traffic"] = tr["bytes_per_launch"]
         roof["traffic_unit"] = "bytes/launch"
