@@ -141,6 +141,65 @@ def cpu_baseline(specs, arrays, budget_s=12.0):
                       % (n, len(specs), cells, t_tot)}
 
 
+# Table I of the paper (workstation, Intel Core i5-6200U): CA-CFAR without and
+# with the integral image, seconds, per (guard, background) cells per side
+PAPER_TABLE1_S = {(4, 8): (0.126, 0.026), (4, 12): (0.201, 0.016), (8, 8): (0.175, 0.015), (8, 12): (0.184, 0.019)}
+
+
+def table1_bench(steps=5, warmup=2):
+    """Table I on the GPU: the DIRECT form (every cell sums its own training
+    cells) against the TILED and PLAIN integral-image forms, at each (guard,
+    background) setting, on a map of the paper's record size (1024 range
+    bins x 600 slow-time frequency bins, FP64) and on a 16384 x 16384 FP32
+    map.  Kernel-sequence time per map with HIP events on one stream."""
+    import torch
+    from paper_2012_11077_amd import cfar2d as C
+    from paper_2012_11077_amd import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    rows = []
+    for name, R, F, dt in [("1024x600 FP64 (paper-sized record)", 1024, 600, "f64"),
+                           ("16384x16384 FP32", 16384, 16384, "f32")]:
+        spec0 = synth.MapSpec(R, F, dt, "exp_ramp", n_targets=max(1, R * F // 300000), guard_r=4, guard_f=4,
+                              train_r=8, train_f=8, pfa=1e-4, seed=(71, R))
+        x = torch.from_numpy(synth.generate(spec0)).to(dev)
+        mask = torch.empty(x.shape, dtype=torch.uint8, device=dev)
+        masks = {}
+        for (g, b) in PAPER_TABLE1_S:
+            win = (g, g, b, b, 1e-4)
+            ms = {}
+            for fname, form in (("direct", C.DIRECT), ("tiled", C.TILED), ("plain", C.PLAIN)):
+                m = C.make_map(x, win, mask)
+                ws = torch.empty(C.workspace_bytes([m], form), dtype=torch.uint8, device=dev)
+                for _ in range(warmup):
+                    C.cfar2d(x, win, form, mask=mask, ws=ws, stream=stream)
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+                ev[0].record(stream)
+                for k in range(steps):
+                    C.cfar2d(x, win, form, mask=mask, ws=ws, stream=stream)
+                    ev[k + 1].record(stream)
+                torch.cuda.synchronize()
+                ms[fname] = float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]))
+                masks[fname] = mask.clone()
+                del ws
+            same = int((masks["direct"] != masks["tiled"]).sum().item())
+            row = {"map": name, "guard": g, "background": b, "window": [2 * (g + b) + 1] * 2,
+                   "direct_ms": round(ms["direct"], 4), "tiled_ms": round(ms["tiled"], 4),
+                   "plain_ms": round(ms["plain"], 4),
+                   "direct_over_tiled": round(ms["direct"] / ms["tiled"], 2),
+                   "direct_over_plain": round(ms["direct"] / ms["plain"], 2),
+                   "mask_cells_direct_vs_tiled_differing": same,
+                   "paper_workstation_s": {"ca_cfar": PAPER_TABLE1_S[(g, b)][0],
+                                           "ii_ca_cfar": PAPER_TABLE1_S[(g, b)][1]}}
+            log(json.dumps(row))
+            rows.append(row)
+        del x, mask, masks
+        torch.cuda.empty_cache()
+    return {"table1": rows, "note": "direct = no integral image (each cell sums its window); tiled/plain = "
+                                    "integral-image forms; paper times are a different machine and map size"}
+
+
 def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
     """The serving workload: n_streams simulated drone streams, each emitting
     frames of its own fixed size at Poisson rate 50 Hz, submitted from
@@ -285,6 +344,8 @@ def main():
                     help="only copy 1 GiB device to device 3 times (the counter scale of rocprofv3 FETCH_SIZE "
                          "and WRITE_SIZE)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving run (prints its JSON)")
+    ap.add_argument("--table1", action="store_true",
+                    help="only the Table I comparison: DIRECT vs TILED vs PLAIN per (guard, background) setting")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the serving run (16 Poisson streams at 50 Hz); 0 skips it")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -321,6 +382,9 @@ def main():
     C.lib()
     if args.serve_only:
         print(json.dumps(serve_bench(args.serve_seconds)), flush=True)
+        return
+    if args.table1:
+        print(json.dumps(table1_bench()), flush=True)
         return
 
     specs, desc = build_workload(args.workload)

@@ -70,8 +70,17 @@ typedef enum { CFAR_F32 = 0, CFAR_F64 = 1 } cfar_dtype;
  *          rows (the row corners) and takes an FP64 row prefix of them across
  *          the strip (the column corners as differences).  The map stays in
  *          its storage type (FP32 or FP64); one pass over X.  Supports
- *          guard_f + train_f <= 247. */
-typedef enum { CFAR_FORM_PLAIN = 0, CFAR_FORM_TILED = 1 } cfar_form;
+ *          guard_f + train_f <= 247.
+ *   DIRECT: no integral image: every cell sums its own training cells (the
+ *          CA-CFAR route that Table I compares the integral image against),
+ *          in FP64 from the map's storage type, then eqs. (1)-(2) as in the
+ *          other forms.  Work per cell grows with the window area.  A
+ *          workgroup stages a 4 x 64 output tile and its window halo in LDS,
+ *          so it supports (4 + 2 hr) x (64 + 2 hf) x element size <= 65536
+ *          bytes (hr = guard_r + train_r, hf = guard_f + train_f; e.g. every
+ *          window of Table I, and hr = hf = 28 in FP64).  sat2d does not take
+ *          this form.  Workspace: the threshold table only. */
+typedef enum { CFAR_FORM_PLAIN = 0, CFAR_FORM_TILED = 1, CFAR_FORM_DIRECT = 2 } cfar_form;
 
 /* CFAR window (Table I, eq. 2): half-widths per axis, in cells.  The outer
  * half-widths are guard + train.  train_r + train_f must be > 0; 0 < pfa < 1. */
@@ -131,7 +140,8 @@ int sat2d(const void *x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, 
 
 /* Device workspace bytes for cfar2d / cfar2d_batched over `n` maps in `form`
  * (PLAIN: the FP64 SAT of the largest map plus its aggregates, plus the
- * threshold tables; TILED: descriptors, work counters and threshold tables).
+ * threshold tables; TILED: descriptors, work counters and threshold tables;
+ * DIRECT: the largest map's threshold table).
  * Returns 0 when an argument is invalid (cfar_last_error() says which). */
 size_t cfar_workspace_bytes(const cfar_map *maps, int32_t n, int32_t form);
 
@@ -141,8 +151,8 @@ size_t cfar_workspace_bytes(const cfar_map *maps, int32_t n, int32_t form);
  * another call until this call's work on `stream` has finished.
  * Errors: CFAR_EINVAL (see the conventions above: rows/cols < 1, ld or
  * ld_mask < cols, negative half-width, train_r + train_f == 0, pfa not in
- * (0,1), NULL x/mask, unknown dtype/form, reserved0 != 0), CFAR_ENOSPC,
- * CFAR_EDEVICE. */
+ * (0,1), NULL x/mask, unknown dtype/form, reserved0 != 0, a window too
+ * wide for the form), CFAR_ENOSPC, CFAR_EDEVICE. */
 int cfar2d(const cfar_map *m, int32_t form, void *ws, size_t ws_bytes, void *stream);
 
 /* Batch flags. */
@@ -161,6 +171,8 @@ enum {
  * map's tile plan depends only on that map's own size, window and dtype, so
  * every map's result is the same alone and in any batch.
  * PLAIN: the per-map FP64 form, one sat2d + stencil per map on `stream`.
+ * DIRECT: one table + direct-sum stencil per map on `stream` (flags other
+ * than 0 are accepted and ignored).
  * Errors as cfar2d; map k's problems are reported with its index. */
 int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags, void *ws,
                    size_t ws_bytes, void *stream);
@@ -269,7 +281,9 @@ int cfar_server_destroy(cfar_server *s);
 /* On the calling thread, on = 1 makes every following TILED launch
  * (cfar2d, cfar2d_with_plan, cfar2d_batched) record a pair of HIP events
  * on its stream right before and right after its persistent kernel; batches
- * are then launched without graph capture.  on = 0 turns it off. */
+ * are then launched without graph capture.  DIRECT launches record them
+ * before the first map's stencil and after the last one's.  on = 0 turns
+ * it off. */
 int cfar_timing_enable(int32_t on);
 
 /* Milliseconds between the two events of the calling thread's last timed

@@ -26,7 +26,7 @@ DEFAULT_PLAN_TABLE = os.path.join(_PKG, "plan_table.txt")
 
 CFAR_OK, CFAR_EINVAL, CFAR_ENOSPC, CFAR_EDEVICE, CFAR_EAGAIN, CFAR_ESHUTDOWN = 0, -1, -2, -3, -4, -5
 F32, F64 = 0, 1
-PLAIN, TILED = 0, 1
+PLAIN, TILED, DIRECT = 0, 1, 2
 BATCH_GRAPH = 1
 STATUS_NAMES = {0: "CFAR_OK", -1: "CFAR_EINVAL", -2: "CFAR_ENOSPC", -3: "CFAR_EDEVICE",
                 -4: "CFAR_EAGAIN", -5: "CFAR_ESHUTDOWN"}
@@ -327,12 +327,12 @@ def _mask_like(x: torch.Tensor) -> torch.Tensor:
 
 
 def timing_enable(on: bool) -> None:
-    """Record HIP events around the persistent kernel of TILED launches (no graphs meanwhile)."""
+    """Record HIP events around the kernels of TILED launches (no graphs meanwhile) and DIRECT launches."""
     _check(lib().cfar_timing_enable(1 if on else 0))
 
 
 def timing_read() -> float:
-    """Kernel milliseconds of the calling thread's last timed TILED launch."""
+    """Kernel milliseconds of the calling thread's last timed TILED or DIRECT launch."""
     v = ctypes.c_double()
     _check(lib().cfar_timing_read(ctypes.byref(v)))
     return v.value

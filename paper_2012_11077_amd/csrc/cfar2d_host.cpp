@@ -89,10 +89,18 @@ int validate_map(const cfar_map *m, int idx, int form)
         return set_error(CFAR_EINVAL, "map %d: guard + train half-width above %d", idx, kMaxHalf);
     if (!(w.pfa > 0.0 && w.pfa < 1.0) || !std::isfinite(w.pfa))
         return set_error(CFAR_EINVAL, "map %d: pfa must lie in (0, 1)", idx);
-    if (form != CFAR_FORM_PLAIN && form != CFAR_FORM_TILED) return set_error(CFAR_EINVAL, "unknown form %d", form);
+    if (form != CFAR_FORM_PLAIN && form != CFAR_FORM_TILED && form != CFAR_FORM_DIRECT)
+        return set_error(CFAR_EINVAL, "unknown form %d", form);
     if (form == CFAR_FORM_TILED && w.guard_f + w.train_f > kMaxTiledHf)
         return set_error(CFAR_EINVAL, "map %d: TILED form supports guard_f + train_f <= %d (use PLAIN)", idx,
                          kMaxTiledHf);
+    if (form == CFAR_FORM_DIRECT) {
+        if (direct_lds_bytes(w.guard_r + w.train_r, w.guard_f + w.train_f, m->dtype) > kDirMaxLds)
+            return set_error(CFAR_EINVAL, "map %d: DIRECT form supports (%d + 2 hr) x (%d + 2 hf) x element size "
+                                          "<= %zu bytes (use TILED or PLAIN)", idx, kDirTH, kDirTW, kDirMaxLds);
+        const int64_t nb = (m->rows + kDirTH - 1) / kDirTH * ((m->cols + kDirTW - 1) / kDirTW);
+        if (nb > INT32_MAX) return set_error(CFAR_EINVAL, "map %d: DIRECT form supports up to 2^31 - 1 tiles", idx);
+    }
     return CFAR_OK;
 }
 
@@ -668,6 +676,28 @@ static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, si
     return CFAR_OK;
 }
 
+// Single map, DIRECT: table, then every cell sums its own window.  Kernel
+// timing (if on) starts before the first map's stencil and stops after the
+// last one's.
+static int run_direct_single(const cfar_map *m, void *ws, size_t ws_bytes, hipStream_t stream, bool first = true,
+                             bool last = true)
+{
+    const size_t need = lut_bytes(m);
+    if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
+    if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
+    MapDesc d = make_desc(m, nullptr, (double *)ws);
+    hipError_t e = launch_lut(nullptr, d, 1, nullptr, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
+    if (first && (e = timing_mark(g_timing.start, stream)) != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
+    e = launch_stencil_direct(d, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(stencil_direct)");
+    if (last) {
+        if ((e = timing_mark(g_timing.stop, stream)) != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
+        if (g_timing.on) g_timing.recorded = true;
+    }
+    return CFAR_OK;
+}
+
 // Single map, PLAIN: FP64 SAT into ws, table, stencil.
 static int run_plain_single(const cfar_map *m, void *ws, size_t ws_bytes, hipStream_t stream)
 {
@@ -771,9 +801,10 @@ size_t cfar_workspace_bytes(const cfar_map *maps, int32_t n, int32_t form)
     if (!maps || n < 1) { set_error(CFAR_EINVAL, "maps is NULL or n < 1"); return 0; }
     for (int i = 0; i < n; ++i)
         if (validate_map(&maps[i], i, form) != CFAR_OK) return 0;
-    if (form == CFAR_FORM_PLAIN) {
+    if (form == CFAR_FORM_PLAIN || form == CFAR_FORM_DIRECT) {
         size_t need = 0;
-        for (int i = 0; i < n; ++i) need = std::max(need, plain_single_ws(&maps[i]));
+        for (int i = 0; i < n; ++i)
+            need = std::max(need, form == CFAR_FORM_PLAIN ? plain_single_ws(&maps[i]) : lut_bytes(&maps[i]));
         return need;
     }
     uint64_t total_units = 0;
@@ -792,6 +823,7 @@ int cfar2d(const cfar_map *m, int32_t form, void *ws, size_t ws_bytes, void *str
     int rc = validate_map(m, 0, form);
     if (rc != CFAR_OK) return rc;
     if (form == CFAR_FORM_PLAIN) return run_plain_single(m, ws, ws_bytes, (hipStream_t)stream);
+    if (form == CFAR_FORM_DIRECT) return run_direct_single(m, ws, ws_bytes, (hipStream_t)stream);
     return run_tiled_single(m, choose_plan(m), ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -819,6 +851,16 @@ int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags,
         if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
         for (int i = 0; i < n; ++i) {
             int rc = run_plain_single(&maps[i], ws, ws_bytes, s);
+            if (rc != CFAR_OK) return rc;
+        }
+        return CFAR_OK;
+    }
+    if (form == CFAR_FORM_DIRECT) {  // one table + one stencil launch per map, in order on the stream
+        size_t need = 0;
+        for (int i = 0; i < n; ++i) need = std::max(need, lut_bytes(&maps[i]));
+        if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
+        for (int i = 0; i < n; ++i) {
+            int rc = run_direct_single(&maps[i], ws, ws_bytes, s, i == 0, i == n - 1);
             if (rc != CFAR_OK) return rc;
         }
         return CFAR_OK;

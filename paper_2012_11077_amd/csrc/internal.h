@@ -112,6 +112,12 @@ hipError_t launch_lut(const MapDesc *descs, const MapDesc &single, int n, uint32
 // Eight-corner stencil over the PLAIN FP64 SAT of one map.
 hipError_t launch_stencil_plain(const MapDesc &d, const double *sat, hipStream_t stream);
 
+// DIRECT form: output tile of one workgroup (rows x columns) and its LDS.
+constexpr int kDirTH = 4, kDirTW = 64;
+constexpr size_t kDirMaxLds = 65536;
+size_t direct_lds_bytes(int hr, int hf, int dtype);
+hipError_t launch_stencil_direct(const MapDesc &d, hipStream_t stream);
+
 // Persistent TILED kernel over all work units in `args`.  One kernel per
 // (k set, dtype, out, ua): kset 24 serves maps planned with k = 2 or 4 (one
 // launch for both), kset 8 maps with k = 8; out = maps may carry the

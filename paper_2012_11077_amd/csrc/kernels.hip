@@ -321,6 +321,79 @@ hipError_t launch_stencil_plain(const MapDesc &d, const double *sat, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
+// DIRECT form: CA-CFAR without the integral image (the comparison route of
+// Table I): every cell sums its own training cells.  A workgroup of four
+// waves owns kDirTH x kDirTW outputs (wave w: row i0 + w, lane: column
+// j0 + lane); the tile and its halo of hr rows and hf columns are staged in
+// LDS in the map's type, cells outside the map as zero (the clipped sum).
+// Along a window row the guard test is the same for the whole wave.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) stencil_direct(MapDesc d)
+{
+    extern __shared__ char direct_lds[];
+    T *tile = (T *)direct_lds;
+    const int R = d.rows, F = d.cols, hr = d.hr, hf = d.hf, gr = d.gr, gf = d.gf;
+    const int tcols = kDirTW + 2 * hf, trows = kDirTH + 2 * hr;
+    const int nbj = (F + kDirTW - 1) / kDirTW;
+    const int i0 = (int)(blockIdx.x / (unsigned)nbj) * kDirTH;
+    const int j0 = (int)(blockIdx.x % (unsigned)nbj) * kDirTW;
+    const T *__restrict__ X = (const T *)d.x;
+    for (int t = threadIdx.x; t < trows * tcols; t += 256) {
+        const int a = t / tcols, b = t - a * tcols;
+        const int r = i0 - hr + a, c = j0 - hf + b;
+        tile[t] = (r >= 0 && r < R && c >= 0 && c < F) ? X[(int64_t)r * d.ld + c] : (T)0;
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = i0 + w, j = j0 + lane;
+    // four partial sums break the chain of dependent FP64 adds
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    auto run = [&](const T *p, int n) {  // p[0 .. n-1]
+        int c = 0;
+        for (; c + 4 <= n; c += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += (double)p[c + u];
+        }
+        for (; c < n; ++c) acc[0] += (double)p[c];
+    };
+    for (int da = -hr; da <= hr; ++da) {
+        const T *row = tile + (w + hr + da) * tcols + lane;  // column j - hf
+        if (da >= -gr && da <= gr) {                           // guard band: both sides of the guard
+            run(row, hf - gf);
+            run(row + hf + gf + 1, hf - gf);
+        } else {
+            run(row, 2 * hf + 1);
+        }
+    }
+    if (i >= R || j >= F) return;
+    const double st = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    const int nt = clip_len(i, hr, R) * clip_len(j, hf, F) - clip_len(i, gr, R) * clip_len(j, gf, F);
+    const double cut = ld_x(X + (int64_t)i * d.ld + j);
+    const double thr = nt > 0 ? d.lut[nt] * st : INFINITY;
+    const int64_t o = (int64_t)i * d.ld_mask + j;
+    d.mask[o] = (uint8_t)(nt > 0 && cut > thr);
+    if (d.train_sum) d.train_sum[o] = st;
+    if (d.thresh) d.thresh[o] = thr;
+}
+
+size_t direct_lds_bytes(int hr, int hf, int dtype)
+{
+    return (size_t)(kDirTH + 2 * hr) * (size_t)(kDirTW + 2 * hf) * (dtype == 0 ? 4 : 8);
+}
+
+hipError_t launch_stencil_direct(const MapDesc &d, hipStream_t stream)
+{
+    const int64_t nb = ((int64_t)d.rows + kDirTH - 1) / kDirTH * (((int64_t)d.cols + kDirTW - 1) / kDirTW);
+    const size_t lds = direct_lds_bytes(d.hr, d.hf, d.dtype);
+    if (d.dtype == 0)
+        hipLaunchKernelGGL(stencil_direct<float>, dim3((unsigned)nb), dim3(256), lds, stream, d);
+    else
+        hipLaunchKernelGGL(stencil_direct<double>, dim3((unsigned)nb), dim3(256), lds, stream, d);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // TILED form: persistent fused kernel, one instantiation per (K, T).
 //
 // One wave owns a work unit: a strip of W = 64*K map columns (the strip's

@@ -3,8 +3,8 @@
 * A cell is near-threshold when |X - T_oracle| <= 1e-5 |T_oracle|; both
   decisions are accepted there, and such cells are counted.
 * Every other cell's mask must match the oracle bit for bit.
-* Training sums: TILED form within 1e-6 relative of the oracle (the bound
-  the precision form is held to); PLAIN form within the rounding of an FP64
+* Training sums: TILED and DIRECT forms within 1e-6 relative of the oracle
+  (the bound the precision form is held to); PLAIN form within the rounding of an FP64
   integral image, 64 * eps64 * (sum of the map) plus 1e-12 relative, since
   both sides take differences of SAT entries that grow with the map.
 """
@@ -37,7 +37,7 @@ def check_full(x_np, window, mask, st=None, thr=None, form="tiled", ref=None):
     out = {"near": int(near.sum()), "max_rel": 0.0, "detections": int(m_o.sum())}
     if st is not None:
         err = np.abs(st - st_o)
-        if form == "tiled":
+        if form in ("tiled", "direct"):
             tol = TILED_REL * np.abs(st_o)
         else:
             tol = 64 * EPS64 * float(np.abs(np.asarray(x_np, dtype=np.float64)).sum()) + 1e-12 * np.abs(st_o)
@@ -51,7 +51,7 @@ def check_full(x_np, window, mask, st=None, thr=None, form="tiled", ref=None):
     if thr is not None:
         fin = np.isfinite(thr_o)
         assert np.array_equal(np.isfinite(thr), fin)
-        if form == "tiled":
+        if form in ("tiled", "direct"):
             np.testing.assert_allclose(thr[fin], thr_o[fin], rtol=2e-6, atol=0)
     return out
 
@@ -68,7 +68,7 @@ def check_cells(x_np, window, rows, cols, mask_vals, st_vals=None, form="tiled",
     out = {"near": int(near.sum()), "max_rel": 0.0, "n": int(len(rows))}
     if st_vals is not None:
         err = np.abs(st_vals - st_o)
-        if form == "tiled":
+        if form in ("tiled", "direct"):
             tol = TILED_REL * np.abs(st_o)
         else:
             tol = 64 * EPS64 * s_total + 1e-12 * np.abs(st_o)

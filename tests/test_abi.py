@@ -60,6 +60,28 @@ def test_invalid_maps_are_rejected_before_any_device_work(L, bad, what):
     assert L.cfar_workspace_bytes(ctypes.byref(m), 1, C.TILED) == 0
 
 
+def test_direct_form_limits(L):
+    """DIRECT stages a 4 x 64 tile and its window halo in 64 KiB of LDS:
+    wider windows are refused before any device work; its workspace is the
+    threshold table only; sat2d does not take it."""
+    m = _map(win=(8, 8, 12, 12, 1e-4))
+    need = L.cfar_workspace_bytes(ctypes.byref(m), 1, C.DIRECT)
+    n_full = 41 * 41 - 17 * 17
+    assert need == ((n_full + 1) * 8 + 255) // 256 * 256      # the table beta(0 .. n_full)
+    m = _map(dtype=C.F64, win=(4, 4, 24, 24, 1e-4))            # (4+56) x (64+56) x 8 = 57600: fits
+    assert L.cfar_workspace_bytes(ctypes.byref(m), 1, C.DIRECT) > 0
+    m = _map(win=(1, 2, 4, 200, 1e-4))                          # (4+10) x (64+404) x 4 = 26208: fits
+    assert L.cfar_workspace_bytes(ctypes.byref(m), 1, C.DIRECT) > 0
+    m = _map(dtype=C.F64, win=(4, 4, 30, 30, 1e-4))             # (4+68) x (64+68) x 8 = 76032: too wide
+    assert L.cfar2d(ctypes.byref(m), C.DIRECT, 0x3000, 1 << 20, None) == C.CFAR_EINVAL
+    assert "DIRECT form supports" in C.last_error()
+    assert L.cfar_workspace_bytes(ctypes.byref(m), 1, C.DIRECT) == 0
+    assert L.sat2d_bytes(10, 10, C.DIRECT) == 0
+    assert L.sat2d(0x1000, C.F32, 10, 10, 10, C.DIRECT, 0x2000, 1 << 20, 0x3000, 1 << 20, None) == C.CFAR_EINVAL
+    ms = (C.Map * 2)(_map(), _map())
+    assert L.cfar2d_batched(ms, 2, C.DIRECT, 0, 0x3000, 16, None) == C.CFAR_ENOSPC
+
+
 def test_workspace_too_small_is_enospc(L):
     m = _map()
     need = L.cfar_workspace_bytes(ctypes.byref(m), 1, C.TILED)

@@ -17,7 +17,7 @@ from parity import check_cells, check_full, sample_cells, say
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-FORMS = {"plain": C.PLAIN, "tiled": C.TILED}
+FORMS = {"plain": C.PLAIN, "tiled": C.TILED, "direct": C.DIRECT}
 
 
 def _run(x_np, window, form, with_outputs=True, x_dev=None):
@@ -32,7 +32,7 @@ def _run(x_np, window, form, with_outputs=True, x_dev=None):
             th.cpu().numpy() if th is not None else None)
 
 
-@pytest.mark.parametrize("form", ["plain", "tiled"])
+@pytest.mark.parametrize("form", ["plain", "tiled", "direct"])
 def test_config0(form):
     spec = synth.config0()
     x, targets = synth.generate_with_targets(spec)
@@ -45,7 +45,7 @@ def test_config0(form):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("form", ["plain", "tiled"])
+@pytest.mark.parametrize("form", ["plain", "tiled", "direct"])
 def test_random_small_maps(form, dtype):
     specs = synth.random_small_specs(40, seed=11 if dtype == "f32" else 12, dtype=dtype)
     for k, spec in enumerate(specs):
@@ -72,7 +72,7 @@ EDGE = [
 ]
 
 
-@pytest.mark.parametrize("form", ["plain", "tiled"])
+@pytest.mark.parametrize("form", ["plain", "tiled", "direct"])
 @pytest.mark.parametrize("case", EDGE, ids=[str(c[:2] + c[2:6]) for c in EDGE])
 def test_edge_shapes(form, case):
     R, F, gr, gf, tr, tf, pfa = case
@@ -84,7 +84,7 @@ def test_edge_shapes(form, case):
     check_full(x, spec.window, mask, st, th, form)
 
 
-@pytest.mark.parametrize("form", ["plain", "tiled"])
+@pytest.mark.parametrize("form", ["plain", "tiled", "direct"])
 def test_strided_and_misaligned(form):
     """ld > cols, ld_mask > cols and a map pointer that is not 16-byte
     aligned (vector paths must fall back)."""
