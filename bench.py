@@ -200,6 +200,61 @@ def table1_bench(steps=5, warmup=2):
                                     "integral-image forms; paper times are a different machine and map size"}
 
 
+def detections_bench(steps=10, warmup=2):
+    """What the detector hands on, on the 16384 x 16384 FP32 map of the
+    precision workload: the TILED detector, then the detection list (count
+    pass + write pass) and the bit-packed mask, each timed with HIP events on
+    one stream; bytes a host copy of each output would move."""
+    import torch
+    from paper_2012_11077_amd import cfar2d as C
+    from paper_2012_11077_amd import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    spec = synth.config2()
+    x = torch.from_numpy(synth.generate(spec)).to(dev)
+    mask = torch.empty(x.shape, dtype=torch.uint8, device=dev)
+    R, F = x.shape
+    m = C.make_map(x, spec.window, mask)
+    ws = torch.empty(C.workspace_bytes([m], C.TILED), dtype=torch.uint8, device=dev)
+    wsd = torch.empty(C.lib().cfar_detections_workspace_bytes(C.ctypes.byref(m)), dtype=torch.uint8, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    C.cfar2d(x, spec.window, C.TILED, mask=mask, ws=ws, stream=stream)
+    C._check(C.lib().cfar_detections(C.ctypes.byref(m), None, 0, cnt.data_ptr(), wsd.data_ptr(), wsd.numel(),
+                                     stream.cuda_stream))
+    torch.cuda.synchronize()
+    n_det = int(cnt.item())
+    out = torch.empty(max(n_det, 1) * 3, dtype=torch.float64, device=dev)
+    words = (F + 31) // 32
+    bits = torch.empty((R, words), dtype=torch.int32, device=dev)
+    steps_fn = {
+        "detector": lambda: C.cfar2d(x, spec.window, C.TILED, mask=mask, ws=ws, stream=stream),
+        "detection_list": lambda: C._check(C.lib().cfar_detections(
+            C.ctypes.byref(m), out.data_ptr(), n_det, cnt.data_ptr(), wsd.data_ptr(), wsd.numel(),
+            stream.cuda_stream)),
+        "mask_pack": lambda: C._check(C.lib().cfar_mask_pack(C.ctypes.byref(m), bits.data_ptr(), words,
+                                                             stream.cuda_stream)),
+    }
+    res = {}
+    for name, fn in steps_fn.items():
+        for _ in range(warmup):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for k in range(steps):
+            fn()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        res[name + "_ms"] = round(float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])), 4)
+    cells = R * F
+    # the list reads the mask twice (count and write passes) and writes 24 B per record
+    res["detection_list_gbs"] = round((2 * cells + 24 * n_det) / (res["detection_list_ms"] / 1e3) / 1e9, 1)
+    res["mask_pack_gbs"] = round((cells + cells / 8) / (res["mask_pack_ms"] / 1e3) / 1e9, 1)
+    res.update({"map": "16384x16384 FP32, guard 4, training 24, Pfa 1e-5, seed 2", "detections": n_det,
+                "host_bytes": {"dense_mask": cells, "packed_mask": R * words * 4, "detection_list": 24 * n_det}})
+    return res
+
+
 def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
     """The serving workload: n_streams simulated drone streams, each emitting
     frames of its own fixed size at Poisson rate 50 Hz, submitted from
@@ -344,6 +399,8 @@ def main():
                     help="only copy 1 GiB device to device 3 times (the counter scale of rocprofv3 FETCH_SIZE "
                          "and WRITE_SIZE)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving run (prints its JSON)")
+    ap.add_argument("--detections", action="store_true",
+                    help="only the detection-list and packed-mask timing on the 16384^2 FP32 map")
     ap.add_argument("--table1", action="store_true",
                     help="only the Table I comparison: DIRECT vs TILED vs PLAIN per (guard, background) setting")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -385,6 +442,9 @@ def main():
         return
     if args.table1:
         print(json.dumps(table1_bench()), flush=True)
+        return
+    if args.detections:
+        print(json.dumps(detections_bench()), flush=True)
         return
 
     specs, desc = build_workload(args.workload)

@@ -275,6 +275,41 @@ int cfar_server_shutdown(cfar_server *s, int32_t drain_queued);
 int cfar_server_destroy(cfar_server *s);
 
 /* ------------------------------------------------------------------------ */
+/* Detection lists and bit-packed masks                                      */
+/* ------------------------------------------------------------------------ */
+
+/* One detection: a cell decided H1 (eq. 1: CUT > T). */
+typedef struct {
+    int32_t row, col;  /* the cell */
+    double cut;        /* X(row, col) as FP64 */
+    double threshold;  /* T of eq. (2) at the cell from the map's threshold
+                          output, NaN when the map has none */
+} cfar_detection;      /* 24 bytes */
+
+/* Device workspace bytes for cfar_detections on map m (0 if m is invalid). */
+size_t cfar_detections_workspace_bytes(const cfar_map *m);
+
+/* The detections of map m -- the cells whose mask byte is nonzero, after
+ * cfar2d / cfar2d_batched wrote m->mask on the same stream -- as records in
+ * row-major order of the cells.  m: host descriptor (x, mask and the
+ * optional threshold are read; win is not).  out: device array of
+ * `capacity` records (may be NULL when capacity is 0); the first
+ * min(count, capacity) records are written, the rest are not.  count:
+ * device int64, receives the number of detections (which may exceed
+ * capacity).  ws: device, >= cfar_detections_workspace_bytes(m), not used by
+ * another call until this one's work on `stream` has finished.  Errors:
+ * CFAR_EINVAL (invalid map fields, capacity < 0, out NULL with capacity > 0,
+ * count or ws NULL), CFAR_ENOSPC, CFAR_EDEVICE. */
+int cfar_detections(const cfar_map *m, cfar_detection *out, int64_t capacity, int64_t *count, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Bit-packed copy of map m's mask: bit u of word w of row r is cell
+ * (r, 32 w + u); bits past the last column are 0.  bits: device,
+ * rows x ld_words uint32, ld_words >= ceil(cols / 32).  One eighth of the
+ * mask's bytes to copy back.  Errors: CFAR_EINVAL, CFAR_EDEVICE. */
+int cfar_mask_pack(const cfar_map *m, uint32_t *bits, int64_t ld_words, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing (benchmarks)                                                */
 /* ------------------------------------------------------------------------ */
 

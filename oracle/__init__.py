@@ -14,6 +14,10 @@ Functions and the passage each one follows:
 * :func:`cfar2d_cells` -- the direct CA-CFAR of Table I (no integral image),
   on a list of cells; used for sampled checks of large maps.
 * :func:`alpha` -- eq. (2), the scale factor, exponent read as -1/N.
+* :func:`detection_list` -- the H1 cells of eq. (1) as records in row-major
+  order (row, col, CUT, T).
+* :func:`pack_mask` -- the mask as bits, 32 cells per word, cell 32 w + u at
+  bit u of word w.
 """
 from __future__ import annotations
 
@@ -144,3 +148,27 @@ def near_threshold(x: np.ndarray, thr: np.ndarray, rel: float = 1e-5) -> np.ndar
     t = np.asarray(thr, dtype=np.float64)
     with np.errstate(invalid="ignore"):
         return np.isfinite(t) & (np.abs(xd - t) <= rel * np.abs(t))
+
+
+def detection_list(mask: np.ndarray, x: np.ndarray, thr=None):
+    """Records of the cells with a nonzero mask, rows outer, columns inner:
+    (row, col, X(row, col), T(row, col) or NaN)."""
+    out = []
+    R, F = mask.shape
+    for i in range(R):
+        for j in range(F):
+            if mask[i, j]:
+                out.append((i, j, float(x[i, j]), float(thr[i, j]) if thr is not None else float("nan")))
+    return out
+
+
+def pack_mask(mask: np.ndarray) -> np.ndarray:
+    """uint32 words, rows x ceil(F/32): bit u of word w is cell (r, 32 w + u)."""
+    R, F = mask.shape
+    words = (F + 31) // 32
+    out = np.zeros((R, words), dtype=np.uint32)
+    for i in range(R):
+        for j in range(F):
+            if mask[i, j]:
+                out[i, j // 32] |= np.uint32(1) << np.uint32(j % 32)
+    return out

@@ -107,12 +107,17 @@ def lib():
         L.cfar_server_destroy.argtypes = [_vp]
         L.cfar_host_alloc.argtypes = [_sz, ctypes.POINTER(_vp)]
         L.cfar_host_free.argtypes = [_vp]
+        L.cfar_detections_workspace_bytes.argtypes = [_PMap]
+        L.cfar_detections_workspace_bytes.restype = _sz
+        L.cfar_detections.argtypes = [_PMap, _vp, _i64, _vp, _vp, _sz, _vp]
+        L.cfar_mask_pack.argtypes = [_PMap, _vp, _i64, _vp]
         L.cfar_timing_enable.argtypes = [_i32]
         L.cfar_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
         for name in ("sat2d", "cfar2d", "cfar2d_batched", "cfar_plan_for", "cfar_plan_load",
                      "cfar2d_with_plan", "cfar_timing_enable", "cfar_timing_read", "cfar_server_create",
                      "cfar_submit", "cfar_poll", "cfar_server_stats_get", "cfar_server_shutdown",
-                     "cfar_server_destroy", "cfar_host_alloc", "cfar_host_free"):
+                     "cfar_server_destroy", "cfar_host_alloc", "cfar_host_free", "cfar_detections",
+                     "cfar_mask_pack"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         table = os.environ.get("CFAR2D_PLAN_TABLE")
@@ -324,6 +329,47 @@ def plan_for(x: torch.Tensor, window) -> Tuple[int, int, int]:
 
 def _mask_like(x: torch.Tensor) -> torch.Tensor:
     return torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+
+
+DETECTION_BYTES = 24   # cfar_detection: int32 row, int32 col, float64 cut, float64 threshold
+
+
+def detections(x: torch.Tensor, mask: torch.Tensor, threshold: Optional[torch.Tensor] = None,
+               capacity: Optional[int] = None, stream=None):
+    """Detections of a map whose mask the detector wrote (same stream): a dict
+    of device tensors ``row``, ``col`` (int32), ``cut``, ``threshold``
+    (float64; NaN without a threshold output), in row-major order of the
+    cells, and ``count`` (the total, which may exceed ``capacity``).  With
+    no capacity given the count is taken first (one synchronisation) and
+    the list sized to it."""
+    m = make_map(x, (0, 0, 0, 1, 0.5), mask, None, threshold)
+    cnt = torch.zeros(1, dtype=torch.int64, device=x.device)
+    ws = _alloc_ws(lib().cfar_detections_workspace_bytes(ctypes.byref(m)), x.device)
+    h = _stream_handle(stream)
+    if capacity is None:
+        _check(lib().cfar_detections(ctypes.byref(m), None, 0, cnt.data_ptr(), ws.data_ptr(), ws.numel(), h))
+        torch.cuda.synchronize(x.device)   # the count was written on the library's stream `h`
+        capacity = int(cnt.item())
+    cap = int(capacity)
+    buf = torch.empty(max(cap, 1) * DETECTION_BYTES // 8, dtype=torch.float64, device=x.device)
+    _check(lib().cfar_detections(ctypes.byref(m), buf.data_ptr() if cap > 0 else None, cap, cnt.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), h))
+    torch.cuda.synchronize(x.device)
+    n = min(int(cnt.item()), cap)
+    rec = buf.view(-1, 3)[:n]
+    rc = rec.view(torch.int32)[:, :2]
+    return {"row": rc[:, 0], "col": rc[:, 1], "cut": rec[:, 1], "threshold": rec[:, 2], "count": int(cnt.item())}
+
+
+def mask_pack(x: torch.Tensor, mask: torch.Tensor, stream=None) -> torch.Tensor:
+    """Bit-packed mask: int32 tensor rows x ceil(cols/32); bit u of word w of
+    row r is cell (r, 32 w + u)."""
+    m = make_map(x, (0, 0, 0, 1, 0.5), mask)
+    R, F = mask.shape
+    words = (F + 31) // 32
+    bits = torch.empty((R, words), dtype=torch.int32, device=x.device)
+    _check(lib().cfar_mask_pack(ctypes.byref(m), bits.data_ptr(), words, _stream_handle(stream)))
+    return bits
 
 
 def timing_enable(on: bool) -> None:

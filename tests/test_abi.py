@@ -82,6 +82,21 @@ def test_direct_form_limits(L):
     assert L.cfar2d_batched(ms, 2, C.DIRECT, 0, 0x3000, 16, None) == C.CFAR_ENOSPC
 
 
+def test_detection_argument_checks(L):
+    m = _map(rows=10, cols=9000)
+    need = L.cfar_detections_workspace_bytes(ctypes.byref(m))
+    nb = 10 * 3                                     # 4096 columns per block
+    assert need == (nb * 4 + 255) // 256 * 256 + (nb * 8 + 255) // 256 * 256
+    assert L.cfar_detections(ctypes.byref(m), None, 5, 0x4000, 0x3000, need, None) == C.CFAR_EINVAL   # out NULL
+    assert L.cfar_detections(ctypes.byref(m), 0x5000, -1, 0x4000, 0x3000, need, None) == C.CFAR_EINVAL
+    assert L.cfar_detections(ctypes.byref(m), None, 0, None, 0x3000, need, None) == C.CFAR_EINVAL     # count NULL
+    assert L.cfar_detections(ctypes.byref(m), None, 0, 0x4000, 0x3000, need - 1, None) == C.CFAR_ENOSPC
+    assert L.cfar_mask_pack(ctypes.byref(m), 0x5000, 281, None) == C.CFAR_EINVAL                    # < ceil(9000/32)
+    assert L.cfar_mask_pack(ctypes.byref(m), None, 282, None) == C.CFAR_EINVAL
+    bad = _map(rows=0)
+    assert L.cfar_detections_workspace_bytes(ctypes.byref(bad)) == 0
+
+
 def test_workspace_too_small_is_enospc(L):
     m = _map()
     need = L.cfar_workspace_bytes(ctypes.byref(m), 1, C.TILED)

@@ -310,3 +310,33 @@ def test_false_alarm_rate_on_exponential_noise(oracle_mod):
             sd = r.std(ddof=1) / math.sqrt(n_maps)
             assert abs(r.mean() - pfa) <= 5 * sd + 1e-12, (pfa, r.mean(), sd)
             assert abs(r.mean() - pfa) <= 0.1 * pfa
+
+
+# ---------------------------------------------------------------------------
+# Detection lists and packed masks (the H1 cells of eq. 1, handed on)
+# ---------------------------------------------------------------------------
+def test_detection_list_order_and_content(oracle_mod):
+    rng = np.random.default_rng(5)
+    m = (rng.random((7, 13)) < 0.2).astype(np.uint8)
+    x = rng.random((7, 13))
+    t = rng.random((7, 13))
+    recs = oracle_mod.detection_list(m, x, t)
+    # row-major order is the lexicographic order of (row, col); one record per set cell
+    idx = [(r[0], r[1]) for r in recs]
+    assert idx == sorted(idx) and len(set(idx)) == len(idx) == int(m.sum())
+    assert idx == [tuple(v) for v in np.argwhere(m != 0).tolist()]
+    for (i, j, c, th) in recs:
+        assert c == x[i, j] and th == t[i, j]
+    assert all(np.isnan(r[3]) for r in oracle_mod.detection_list(m, x))
+    assert oracle_mod.detection_list(np.zeros((3, 4), np.uint8), x[:3, :4]) == []
+
+
+def test_pack_mask_round_trip(oracle_mod):
+    rng = np.random.default_rng(6)
+    for F in (1, 31, 32, 33, 100):
+        m = (rng.random((5, F)) < 0.5).astype(np.uint8)
+        p = oracle_mod.pack_mask(m)
+        assert p.shape == (5, (F + 31) // 32)
+        bits = np.unpackbits(p.view(np.uint8), axis=1, bitorder="little")[:, :F]
+        assert np.array_equal(bits, m)
+        assert int(sum(bin(int(v)).count("1") for v in p.ravel())) == int(m.sum())
