@@ -229,3 +229,50 @@ def random_small_specs(n: int, seed: int, max_rows: int = 96, max_cols: int = 96
                            guard_r=gr, guard_f=gf, train_r=tr, train_f=tf, pfa=pfa,
                            seed=(seed, k)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Raw radar records (the input of the primary signal processing, Sec. II.A):
+# N traces of M fast-time samples, stored trace by trace.
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class RawSpec:
+    """One synthetic UWB record: static clutter, a per-trace DC offset and
+    fast-time drift, white noise, and a breathing target whose echo (a
+    Gaussian monocycle) moves back and forth in range at the breathing
+    rate."""
+
+    n_traces: int = 600            # slow time (the paper: 600 traces)
+    n_samples: int = 1024          # fast time (the paper: 1024 samples)
+    fs_slow: float = 20.0          # traces per second (not stated in the paper)
+    target_bin: int = 400          # range sample of the target's echo
+    target_amp: float = 1.0
+    breath_hz: float = 0.3         # the paper's actuator: 0.3 Hz
+    breath_samples: float = 1.3    # peak displacement in fast-time samples (~1 cm at 39 GS/s)
+    pulse_width: float = 6.0       # monocycle width in samples
+    clutter_amp: float = 3.0
+    noise: float = 0.05
+    dc_sigma: float = 0.2
+    drift_sigma: float = 1e-3
+    dtype: str = "f32"
+    seed: Sequence[int] = (9,)
+
+
+def generate_raw(spec: RawSpec) -> np.ndarray:
+    """Draw the record, shape (n_traces, n_samples).  Draw order: clutter
+    profile, DC offsets, drifts, breathing phase, noise."""
+    rng = _rng(spec.seed)
+    N, M = spec.n_traces, spec.n_samples
+    m = np.arange(M, dtype=np.float64)
+    clutter = spec.clutter_amp * rng.standard_normal(M) * np.exp(-m / max(1.0, M / 4.0))
+    dc = spec.dc_sigma * rng.standard_normal(N)
+    drift = spec.drift_sigma * rng.standard_normal(N)
+    phase = rng.uniform(0.0, 2.0 * math.pi)
+    noise = spec.noise * rng.standard_normal((N, M))
+    t = np.arange(N, dtype=np.float64) / spec.fs_slow
+    centre = spec.target_bin + spec.breath_samples * np.sin(2.0 * math.pi * spec.breath_hz * t + phase)
+    u = (m[None, :] - centre[:, None]) / spec.pulse_width
+    echo = spec.target_amp * (-u) * np.exp(-0.5 * u * u)          # Gaussian monocycle
+    raw = clutter[None, :] + dc[:, None] + drift[:, None] * m[None, :] + echo + noise
+    return raw.astype(DTYPES[spec.dtype])
