@@ -255,6 +255,45 @@ def detections_bench(steps=10, warmup=2):
     return res
 
 
+def mapbuild_bench(steps=10, warmup=2):
+    """Building the map from raw records (cfar_map_build) then the TILED
+    detector, timed with HIP events on one stream: a record of the paper's
+    size (600 traces x 1024 samples) and a long one (4000 x 16384).  Table
+    II's SBC times of the same steps are context (another machine)."""
+    import torch
+    from paper_2012_11077_amd import cfar2d as C
+    from paper_2012_11077_amd import synth
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    rows = []
+    for N, M in ((600, 1024), (4000, 16384)):
+        spec = synth.RawSpec(n_traces=N, n_samples=M, target_bin=M * 2 // 3, seed=(12, N))
+        raw = torch.from_numpy(synth.generate_raw(spec)).to(dev)
+        win = (2, 2, 4, 4, 1e-4)
+        res = {}
+        for name, fn in (("map_build", lambda: C.build_map(raw, spec.fs_slow, stream=stream)),
+                         ("map_build_and_cfar", lambda: C.cfar2d(C.build_map(raw, spec.fs_slow, stream=stream),
+                                                                 win, C.TILED, stream=stream))):
+            for _ in range(warmup):
+                fn()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+            ev[0].record(stream)
+            for k in range(steps):
+                fn()
+                ev[k + 1].record(stream)
+            torch.cuda.synchronize()
+            res[name + "_ms"] = round(float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])), 4)
+        k0, nb = C.map_bins(N, spec.fs_slow)
+        res.update({"record": "%d traces x %d samples FP32" % (N, M), "band_bins": nb,
+                    "raw_gbs": round(N * M * 4 / (res["map_build_ms"] / 1e3) / 1e9, 1)})
+        log(json.dumps(res))
+        rows.append(res)
+    return {"mapbuild": rows, "paper_sbc_s": {"signal_processing_fast_time": 12.29,
+                                              "signal_processing_slow_time": 16.37, "ii_ca_cfar": 1.17},
+            "note": "times include allocations of the map and workspace by the Python binding"}
+
+
 def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
     """The serving workload: n_streams simulated drone streams, each emitting
     frames of its own fixed size at Poisson rate 50 Hz, submitted from
@@ -399,6 +438,8 @@ def main():
                     help="only copy 1 GiB device to device 3 times (the counter scale of rocprofv3 FETCH_SIZE "
                          "and WRITE_SIZE)")
     ap.add_argument("--serve-only", action="store_true", help="only the serving run (prints its JSON)")
+    ap.add_argument("--mapbuild", action="store_true",
+                    help="only the map-building timing (raw record -> map -> CA-CFAR)")
     ap.add_argument("--detections", action="store_true",
                     help="only the detection-list and packed-mask timing on the 16384^2 FP32 map")
     ap.add_argument("--table1", action="store_true",
@@ -445,6 +486,9 @@ def main():
         return
     if args.detections:
         print(json.dumps(detections_bench()), flush=True)
+        return
+    if args.mapbuild:
+        print(json.dumps(mapbuild_bench()), flush=True)
         return
 
     specs, desc = build_workload(args.workload)

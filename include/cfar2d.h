@@ -275,6 +275,45 @@ int cfar_server_shutdown(cfar_server *s, int32_t drain_queued);
 int cfar_server_destroy(cfar_server *s);
 
 /* ------------------------------------------------------------------------ */
+/* Building the map from a raw record (Sec. II.A)                            */
+/* ------------------------------------------------------------------------ */
+
+/* Parameters of the primary signal processing.  The paper names the steps
+ * and the respiration band (0.3-0.8 Hz); the rest is not stated there. */
+typedef struct {
+    double fs_slow;     /* slow-time sample rate, traces per second, > 0        */
+    double f_lo, f_hi;  /* band kept, Hz, 0 <= f_lo <= f_hi (inclusive)         */
+    int32_t mean_len;   /* slow-time mean filter length, odd, 1..1023 (1: none) */
+    int32_t out_dtype;  /* type of the map written: CFAR_F32 or CFAR_F64        */
+} cfar_mapbuild_params;
+
+/* The DFT bins the band keeps for n_traces traces: k = first_bin ..
+ * first_bin + n_bins - 1 with first_bin = ceil(f_lo N / fs), last =
+ * min(floor(f_hi N / fs), N / 2).  CFAR_EINVAL if the band holds none, or
+ * n_traces is outside [1, 4000], or a parameter is out of range. */
+int cfar_map_bins(int64_t n_traces, const cfar_mapbuild_params *params, int32_t *first_bin, int32_t *n_bins);
+
+/* Device workspace bytes for cfar_map_build (0 if an argument is invalid). */
+size_t cfar_map_build_workspace_bytes(int64_t n_traces, int64_t n_samples, const cfar_mapbuild_params *params);
+
+/* The range x slow-time-frequency power map of a raw record (Sec. II.A):
+ * raw: device, n_traces traces of n_samples fast-time samples, trace n at
+ * raw + n * ld_raw (elements, raw_dtype CFAR_F32 or CFAR_F64).  Steps: per
+ * trace, DC-shift removal and linear-trend subtraction (least-squares line
+ * over the sample index); per range bin, the centred mean filter of
+ * mean_len along slow time (averaging the samples inside the record at its
+ * ends); normalisation by the record's largest filtered magnitude (one
+ * scalar; an all-zero record gives a zero map); per range bin, the DFT over
+ * slow time, kept for the band's bins, as power |F(k)|^2.  map_out: device,
+ * n_samples rows (range bins) x n_bins columns (band bins, see
+ * cfar_map_bins), leading dimension ld_map >= n_bins, params->out_dtype; it
+ * is a map that cfar2d takes as is.  FP64 arithmetic throughout.  Errors:
+ * CFAR_EINVAL, CFAR_ENOSPC, CFAR_EDEVICE. */
+int cfar_map_build(const void *raw, int32_t raw_dtype, int64_t n_traces, int64_t n_samples, int64_t ld_raw,
+                   const cfar_mapbuild_params *params, void *map_out, int64_t ld_map, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Detection lists and bit-packed masks                                      */
 /* ------------------------------------------------------------------------ */
 

@@ -43,6 +43,11 @@ class Window(ctypes.Structure):
                 ("train_r", ctypes.c_int32), ("train_f", ctypes.c_int32), ("pfa", ctypes.c_double)]
 
 
+class MapBuildParams(ctypes.Structure):
+    _fields_ = [("fs_slow", ctypes.c_double), ("f_lo", ctypes.c_double), ("f_hi", ctypes.c_double),
+                ("mean_len", ctypes.c_int32), ("out_dtype", ctypes.c_int32)]
+
+
 class Map(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("ld", ctypes.c_int64),
@@ -107,6 +112,11 @@ def lib():
         L.cfar_server_destroy.argtypes = [_vp]
         L.cfar_host_alloc.argtypes = [_sz, ctypes.POINTER(_vp)]
         L.cfar_host_free.argtypes = [_vp]
+        _PMB = ctypes.POINTER(MapBuildParams)
+        L.cfar_map_bins.argtypes = [_i64, _PMB, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+        L.cfar_map_build_workspace_bytes.argtypes = [_i64, _i64, _PMB]
+        L.cfar_map_build_workspace_bytes.restype = _sz
+        L.cfar_map_build.argtypes = [_vp, _i32, _i64, _i64, _i64, _PMB, _vp, _i64, _vp, _sz, _vp]
         L.cfar_detections_workspace_bytes.argtypes = [_PMap]
         L.cfar_detections_workspace_bytes.restype = _sz
         L.cfar_detections.argtypes = [_PMap, _vp, _i64, _vp, _vp, _sz, _vp]
@@ -117,7 +127,7 @@ def lib():
                      "cfar2d_with_plan", "cfar_timing_enable", "cfar_timing_read", "cfar_server_create",
                      "cfar_submit", "cfar_poll", "cfar_server_stats_get", "cfar_server_shutdown",
                      "cfar_server_destroy", "cfar_host_alloc", "cfar_host_free", "cfar_detections",
-                     "cfar_mask_pack"):
+                     "cfar_mask_pack", "cfar_map_bins", "cfar_map_build"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
         table = os.environ.get("CFAR2D_PLAN_TABLE")
@@ -329,6 +339,34 @@ def plan_for(x: torch.Tensor, window) -> Tuple[int, int, int]:
 
 def _mask_like(x: torch.Tensor) -> torch.Tensor:
     return torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+
+
+def map_bins(n_traces: int, fs_slow: float, f_lo: float = 0.3, f_hi: float = 0.8) -> Tuple[int, int]:
+    """(first DFT bin, number of bins) the band keeps for n_traces traces."""
+    p = MapBuildParams(float(fs_slow), float(f_lo), float(f_hi), 1, F32)
+    k0, nb = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().cfar_map_bins(int(n_traces), ctypes.byref(p), ctypes.byref(k0), ctypes.byref(nb)))
+    return int(k0.value), int(nb.value)
+
+
+def build_map(raw: torch.Tensor, fs_slow: float, f_lo: float = 0.3, f_hi: float = 0.8, mean_len: int = 5,
+              out_dtype=torch.float32, stream=None) -> torch.Tensor:
+    """Range x slow-time-frequency power map (Sec. II.A) of a raw record
+    ``raw`` (n_traces x n_samples, one trace per row, on the device)."""
+    _check_2d(raw, "raw")
+    N, M = raw.shape
+    p = MapBuildParams(float(fs_slow), float(f_lo), float(f_hi), int(mean_len),
+                       F32 if out_dtype == torch.float32 else F64)
+    _, nb = map_bins(N, fs_slow, f_lo, f_hi)
+    out = torch.empty((M, nb), dtype=out_dtype, device=raw.device)
+    need = lib().cfar_map_build_workspace_bytes(N, M, ctypes.byref(p))
+    if need == 0:
+        raise CfarError(CFAR_EINVAL, last_error())
+    ws = _alloc_ws(need, raw.device)
+    ld = raw.stride(0) if N > 1 else M
+    _check(lib().cfar_map_build(raw.data_ptr(), _dtype_code(raw), N, M, ld, ctypes.byref(p), out.data_ptr(), nb,
+                                ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+    return out
 
 
 DETECTION_BYTES = 24   # cfar_detection: int32 row, int32 col, float64 cut, float64 threshold

@@ -97,6 +97,29 @@ def test_detection_argument_checks(L):
     assert L.cfar_detections_workspace_bytes(ctypes.byref(bad)) == 0
 
 
+def test_map_build_argument_checks(L):
+    P = C.MapBuildParams
+    k0, nb = ctypes.c_int32(), ctypes.c_int32()
+    assert L.cfar_map_bins(600, ctypes.byref(P(20.0, 0.3, 0.8, 5, C.F32)), ctypes.byref(k0), ctypes.byref(nb)) == 0
+    assert (k0.value, nb.value) == (9, 16)                 # bins 9..24 of 600 traces at 20 Hz
+    for p, n in ((P(0.0, 0.3, 0.8, 5, 0), 600), (P(20.0, 0.9, 0.8, 5, 0), 600), (P(20.0, 0.31, 0.32, 5, 0), 600),
+                 (P(20.0, 0.3, 0.8, 5, 0), 4001), (P(20.0, 0.3, 0.8, 5, 0), 0)):
+        assert L.cfar_map_bins(n, ctypes.byref(p), ctypes.byref(k0), ctypes.byref(nb)) == C.CFAR_EINVAL
+        assert L.cfar_map_build_workspace_bytes(n, 1024, ctypes.byref(p)) == 0
+    good = P(20.0, 0.3, 0.8, 5, C.F32)
+    need = L.cfar_map_build_workspace_bytes(600, 1024, ctypes.byref(good))
+    assert need >= 600 * 1024 * 8
+    for p in (P(20.0, 0.3, 0.8, 4, 0), P(20.0, 0.3, 0.8, 1025, 0), P(20.0, 0.3, 0.8, 5, 7)):   # even / long L, dtype
+        assert L.cfar_map_build(0x1000, C.F32, 600, 1024, 1024, ctypes.byref(p), 0x2000, 16, 0x3000, need,
+                                None) == C.CFAR_EINVAL
+    assert L.cfar_map_build(0x1000, C.F32, 600, 1024, 1000, ctypes.byref(good), 0x2000, 16, 0x3000, need,
+                            None) == C.CFAR_EINVAL           # ld_raw < n_samples
+    assert L.cfar_map_build(0x1000, C.F32, 600, 1024, 1024, ctypes.byref(good), 0x2000, 15, 0x3000, need,
+                            None) == C.CFAR_EINVAL           # ld_map < bins
+    assert L.cfar_map_build(0x1000, C.F32, 600, 1024, 1024, ctypes.byref(good), 0x2000, 16, 0x3000, need - 1,
+                            None) == C.CFAR_ENOSPC
+
+
 def test_workspace_too_small_is_enospc(L):
     m = _map()
     need = L.cfar_workspace_bytes(ctypes.byref(m), 1, C.TILED)
