@@ -415,9 +415,6 @@ hipError_t launch_stencil_direct(const MapDesc &d, hipStream_t stream)
 // Global-memory pointers (address space 1): descriptors hand the kernels
 // generic pointers, which would otherwise compile to flat accesses.
 #define CFAR_GLOBAL __attribute__((address_space(1)))
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
 template <typename T>
 __device__ __forceinline__ const CFAR_GLOBAL T *gbl(const T *p) { return (const CFAR_GLOBAL T *)p; }
 template <typename T>
@@ -441,26 +438,15 @@ __device__ __forceinline__ void ldk(const CFAR_GLOBAL char *row, int c, int F, b
 {
     if constexpr ((MODE & 3) != kGeneral) {
         const uint32_t off = (MODE & 3) == kEdge && out ? 0u : (uint32_t)c * (uint32_t)sizeof(T);
-        if constexpr ((MODE & kElem) != 0) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) v[k] = *(const CFAR_GLOBAL T *)(row + off + (uint32_t)(k * sizeof(T)));
-        } else if constexpr (sizeof(T) == 4) {
-            if constexpr (K == 2) {
-                const f32x2 f = *(const CFAR_GLOBAL f32x2 *)(row + off);
-                v[0] = f.x; v[1] = f.y;
-            } else {
-#pragma unroll
-                for (int q = 0; q < K / 4; ++q) {
-                    const f32x4 f = *(const CFAR_GLOBAL f32x4 *)(row + off + 16u * q);
-                    v[4 * q + 0] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
-                }
-            }
+        // K values in one (or two) vector loads, stated as unaligned copies:
+        // rows need not be 16-byte aligned (the memory runs in
+        // unaligned-access mode)
+        if constexpr (K * sizeof(T) == 8) {
+            __builtin_memcpy((char *)v, (const char *)(row + off), 8);
         } else {
 #pragma unroll
-            for (int q = 0; q < K / 2; ++q) {
-                const f64x2 f = *(const CFAR_GLOBAL f64x2 *)(row + off + 16u * q);
-                v[2 * q + 0] = f.x; v[2 * q + 1] = f.y;
-            }
+            for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q)
+                __builtin_memcpy((char *)v + 16 * q, (const char *)(row + off + 16u * q), 16);
         }
     } else {
 #pragma unroll
@@ -805,7 +791,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
     auto interior = [&](auto full_tag, int r0, int r1) {
         constexpr bool FULL = decltype(full_tag)::value;
         if (r0 >= r1) return;
-        constexpr int PD = (MODE & kElem) ? 2 : FULL ? prefetch_rows_full<K, T>() : prefetch_rows<K, T>();
+        constexpr int PD = FULL ? prefetch_rows_full<K, T>() : prefetch_rows<K, T>();
         constexpr int NL = FULL ? 1 : 3;  // global loads per row
         const int D = FULL ? 2 * hr + 2 : 2 * gr + 2;
         const int hw = FULL ? hr : gr;  // half-width of the rows the ring serves
@@ -826,11 +812,11 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         uint32_t so_glead = (uint32_t)(r0 + gr - row_lo) * ldb;
         uint32_t so_lag = 0;
         auto load = [&](T(&b)[NL][K]) {
-            ldk_buf<K, T, (MODE & kElem) != 0>(rsx, voff, so_lead, b[0]);
+            ldk_buf<K, T, false>(rsx, voff, so_lead, b[0]);
             so_lead += ldb;
             if constexpr (!FULL) {
-                ldk_buf<K, T, (MODE & kElem) != 0>(rsx, voff, so_glead, b[1]);
-                ldk_buf<K, T, (MODE & kElem) != 0>(rsx, voff, so_lag, b[2]);
+                ldk_buf<K, T, false>(rsx, voff, so_glead, b[1]);
+                ldk_buf<K, T, false>(rsx, voff, so_lag, b[2]);
                 so_glead += ldb;
                 so_lag += ldb;
             }
@@ -841,7 +827,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             uint32_t so = (uint32_t)(hr - hw) * ldb;  // row r0-hw-1
             for (int i = 0; i < D - 1; ++i) {         // rows r0-hw-1 .. r0+hw-1
                 T v[K];
-                ldk_buf<K, T, (MODE & kElem) != 0>(rsx, voff, so, v);
+                ldk_buf<K, T, false>(rsx, voff, so, v);
                 T *p = ring_at(sl);
 #pragma unroll
                 for (int k = 0; k < K; ++k) p[k] = v[k];
@@ -1044,12 +1030,10 @@ __device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk
     // fall inside the strip, on lane boundaries
     const bool left_ok = cs >= 0 || (cs % K) == 0;
     const bool edge_ok = F >= K && ((F - cs) % K == 0 || cs + W <= F) && left_ok;
-    // vector loads need 16-byte aligned rows and strip start
-    const bool xvec = (d.vec_ok & 1) != 0 && (cs % (16 / (int)sizeof(T))) == 0;
     T *rg = (T *)ring;
-    if (halo_ok && inside && (UA || xvec)) {
+    if (halo_ok && inside) {
         fused_unit<K, T, UA ? (kFast | kElem) : kFast, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
-    } else if (halo_ok && edge_ok && (UA || xvec)) {
+    } else if (halo_ok && edge_ok) {
         fused_unit<K, T, UA ? (kEdge | kElem) : kEdge, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
     } else {
         fused_unit<K, T, kGeneral, OUT>(d, strip, rchunk, strip * d.tw - d.halo_f, qo, qi, rg, ring_bytes, lane);
