@@ -309,13 +309,12 @@ static int ring_budget()
 struct KClass {
     int kset, dtype;  // kset 24: maps planned with k = 2 or 4; 8: k = 8
     bool out;         // maps of the class may write the optional outputs
-    bool ua;          // the maps' rows are not 16-byte aligned
     uint32_t unit_off, units, blocks;
     int ring_bytes;   // LDS ring per wave of its launch (largest need among the maps)
 };
-static int class_slot(int kset, int dtype, bool out, bool ua)
+static int class_slot(int kset, int dtype, bool out)
 {
-    return (((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0)) * 2 + (ua ? 1 : 0);
+    return ((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0);
 }
 static bool has_outputs(const cfar_map *m) { return m->train_sum != nullptr || m->threshold != nullptr; }
 
@@ -494,11 +493,11 @@ static int enqueue_tiled_batch(BatchCtx *ctx, const Slot &sl, const TiledLayout 
         a.descs = descs;
         a.unit_base = (const uint32_t *)(ws + L.off_base);
         a.unit_map = (const uint32_t *)(ws + L.off_umap) + c.unit_off;
-        a.counter = &hdr->counter[class_slot(c.kset, c.dtype, c.out, c.ua)];
+        a.counter = &hdr->counter[class_slot(c.kset, c.dtype, c.out)];
         a.total_units = c.units;
         a.n_maps = n;
         a.ring_bytes = c.ring_bytes;
-        e = launch_fused(a, c.kset, c.dtype, c.out, c.ua, cs);
+        e = launch_fused(a, c.kset, c.dtype, c.out, cs);
         if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
     }
     for (int i = 0; i < n_side; ++i) {
@@ -537,14 +536,13 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
     std::vector<std::vector<int>> members;
     for (int i = 0; i < n; ++i) {
         const int ks = kset_of(plans[i].k), dt = maps[i].dtype;
-        const bool out = has_outputs(&maps[i]), ua = !rows_aligned(&maps[i]);
+        const bool out = has_outputs(&maps[i]);
         size_t c = 0;
-        while (c < classes.size() && !(classes[c].kset == ks && classes[c].dtype == dt && classes[c].out == out &&
-                                       classes[c].ua == ua))
+        while (c < classes.size() && !(classes[c].kset == ks && classes[c].dtype == dt && classes[c].out == out))
             ++c;
         if (c == classes.size()) {
             KClass kc;
-            kc.kset = ks; kc.dtype = dt; kc.out = out; kc.ua = ua; kc.unit_off = 0; kc.units = 0; kc.blocks = 0;
+            kc.kset = ks; kc.dtype = dt; kc.out = out; kc.unit_off = 0; kc.units = 0; kc.blocks = 0;
             kc.ring_bytes = 0;
             classes.push_back(kc);
             members.emplace_back();
@@ -570,8 +568,7 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
         classes[c].unit_off = off;
         off += classes[c].units;
         const int resident =
-            fused_resident_blocks(classes[c].kset, classes[c].dtype, classes[c].out, classes[c].ua,
-                                  classes[c].ring_bytes);
+            fused_resident_blocks(classes[c].kset, classes[c].dtype, classes[c].out, classes[c].ring_bytes);
         classes[c].blocks = (uint32_t)std::min<uint64_t>(classes[c].units, (uint64_t)resident);
         std::stable_sort(members[c].begin(), members[c].end(),
                          [&](int a, int b) { return units_of(plans[a]) > units_of(plans[b]); });
@@ -603,8 +600,8 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
     }
     uint64_t sig = 1469598103934665603ull;  // FNV-1a over the class layout
     for (const KClass &c : classes) {
-        const uint32_t f[8] = {(uint32_t)c.kset, (uint32_t)c.dtype, (uint32_t)c.out, (uint32_t)c.ua,
-                               c.unit_off,         c.units,            c.blocks,         (uint32_t)c.ring_bytes};
+        const uint32_t f[7] = {(uint32_t)c.kset, (uint32_t)c.dtype, (uint32_t)c.out, c.unit_off, c.units, c.blocks,
+                               (uint32_t)c.ring_bytes};
         for (uint32_t v : f) { sig ^= v; sig *= 1099511628211ull; }
     }
 
@@ -668,7 +665,7 @@ static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, si
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
     e = timing_mark(g_timing.start, stream);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
-    e = launch_fused(a, kset_of(p.k), m->dtype, has_outputs(m), !rows_aligned(m), stream);
+    e = launch_fused(a, kset_of(p.k), m->dtype, has_outputs(m), stream);
     if (e != hipSuccess) return hip_error(e, "launch(fused_kernel)");
     e = timing_mark(g_timing.stop, stream);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");

@@ -35,7 +35,7 @@ struct MapDesc {
     int32_t n_strips;     // TILED: strips across the columns
     int32_t n_rchunks;    // TILED: row chunks
     int32_t n_full;       // training cells of an unclipped window
-    int32_t vec_ok;       // bits: 1 x rows aligned, 2 mask rows aligned, 4 unit row span < 2^31 bytes
+    int32_t vec_ok;       // bits: 1 x rows 16-byte aligned (not needed by the loads), 2 mask rows aligned, 4 unit row span < 2^31 bytes
     int32_t pad0;
 };
 static_assert(sizeof(MapDesc) == 128, "MapDesc must stay 128 bytes");
@@ -58,7 +58,7 @@ struct FusedArgs {
 // (header + descriptors + unit tables) with one host-to-device copy; the
 // threshold tables that follow are filled on the device.
 struct BatchHeader {
-    uint32_t counter[16];  // one work counter per kernel class (k set, dtype, outputs, alignment)
+    uint32_t counter[16];  // one work counter per kernel class (k set, dtype, outputs); 8 used
     uint32_t n_maps;
     uint32_t total_units;
     uint32_t pad[46];
@@ -119,14 +119,13 @@ size_t direct_lds_bytes(int hr, int hf, int dtype);
 hipError_t launch_stencil_direct(const MapDesc &d, hipStream_t stream);
 
 // Persistent TILED kernel over all work units in `args`.  One kernel per
-// (k set, dtype, out, ua): kset 24 serves maps planned with k = 2 or 4 (one
+// (k set, dtype, out): kset 24 serves maps planned with k = 2 or 4 (one
 // launch for both), kset 8 maps with k = 8; out = maps may carry the
-// optional training-sum / threshold outputs; ua = the maps' rows are not
-// 16-byte aligned (element loads).
-hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, bool ua, hipStream_t stream);
+// optional training-sum / threshold outputs.
+hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, hipStream_t stream);
 
 // Number of persistent workgroups of that kernel that fit the device.
-int fused_resident_blocks(int kset, int dtype, bool out, bool ua, int ring_bytes);
+int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes);
 
 constexpr int kFusedThreads = 64;  // one wave per workgroup: LDS is sized per wave
 constexpr int kMaxK = 8;

@@ -423,9 +423,7 @@ __device__ __forceinline__ CFAR_GLOBAL T *gbl_w(T *p) { return (CFAR_GLOBAL T *)
 // Work-unit modes of the TILED kernel.  FAST: every lane's K columns lie
 // inside the map.  EDGE: a lane's K columns lie all inside or all outside the
 // map (a strip at the left or right border).  GENERAL: anything else.
-// kElem added to FAST or EDGE: the map's rows are not 16-byte aligned, so a
-// lane loads its K values one by one (still straight-line, no clamping).
-enum { kGeneral = 0, kEdge = 1, kFast = 2, kElem = 4 };
+enum { kGeneral = 0, kEdge = 1, kFast = 2 };
 
 // Loads of K consecutive values of one row (row: wave-uniform byte pointer)
 // starting at strip column c.  FAST: vector load.  EDGE: vector load, from
@@ -510,22 +508,14 @@ constexpr int warm_rows() { return K * sizeof(T) >= 32 ? 4 : 8; }
 constexpr int kBufferFlags = 0x00020000;
 
 // K consecutive values of one row through a buffer resource: lane byte
-// offset voff, wave-uniform row byte offset soff; 16-byte aligned, or
-// element by element (ELEM).
-template <int K, typename T, bool ELEM>
+// offset voff, wave-uniform row byte offset soff (any alignment of the
+// element type: the memory runs in unaligned-access mode).
+template <int K, typename T>
 __device__ __forceinline__ void ldk_buf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T (&v)[K])
 {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    if constexpr (ELEM) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if constexpr (sizeof(T) == 4)
-                v[k] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff + 4u * k, soff, 0));
-            else
-                v[k] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 8u * k, soff, 0));
-        }
-    } else if constexpr (K * sizeof(T) == 8) {
+    if constexpr (K * sizeof(T) == 8) {
         const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
         __builtin_memcpy(v, &w, 8);
     } else {
@@ -536,7 +526,6 @@ __device__ __forceinline__ void ldk_buf(__amdgpu_buffer_rsrc_t rs, uint32_t voff
         }
     }
 }
-
 // FAST units: the strip's output columns are at least hf away from both map
 // borders (only rows can be clipped: N = n_full on interior rows).  EDGE
 // units: a lane's K columns are all inside or all outside the map; interior
@@ -686,32 +675,22 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
     auto decide_fast = [&](const T(&xcut)[K], uint32_t(&bits)[(K + 3) / 4]) {
 #pragma unroll
         for (int q = 0; q < (K + 3) / 4; ++q) bits[q] = 0u;
-        if constexpr (MODE == kFast || MODE == kEdge) {
-            // every corner read is issued before the first is used: the LDS
-            // round trips overlap instead of following one another (the
-            // element-load variants keep the plain order: registers run short)
-            double oh[K], ol[K], ih[K], il[K];
+        // every corner read is issued before the first is used: the LDS
+        // round trips overlap instead of following one another
+        double oh[K], ol[K], ih[K], il[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                oh[k] = rd_oh.get(qo, k);
-                ol[k] = rd_ol.get(qo, k);
-                ih[k] = rd_ih.get(qi, k);
-                il[k] = rd_il.get(qi, k);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+        for (int k = 0; k < K; ++k) {
+            oh[k] = rd_oh.get(qo, k);
+            ol[k] = rd_ol.get(qo, k);
+            ih[k] = rd_ih.get(qi, k);
+            il[k] = rd_il.get(qi, k);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const double beta = BM == kEdge ? beta_lane[BM == kEdge ? k : 0] : beta_full;
-                const double thr = beta * ((oh[k] - ol[k]) - (ih[k] - il[k]));
-                bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
-            }
-        } else {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const double beta = BM == kEdge ? beta_lane[BM == kEdge ? k : 0] : beta_full;
-                const double thr = beta * train_sum_at(k);
-                bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
-            }
+        for (int k = 0; k < K; ++k) {
+            const double beta = BM == kEdge ? beta_lane[BM == kEdge ? k : 0] : beta_full;
+            const double thr = beta * ((oh[k] - ol[k]) - (ih[k] - il[k]));
+            bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
         }
     };
     auto output_fast = [&](int r, const T(&xcut)[K]) {
@@ -812,11 +791,11 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         uint32_t so_glead = (uint32_t)(r0 + gr - row_lo) * ldb;
         uint32_t so_lag = 0;
         auto load = [&](T(&b)[NL][K]) {
-            ldk_buf<K, T, false>(rsx, voff, so_lead, b[0]);
+            ldk_buf<K, T>(rsx, voff, so_lead, b[0]);
             so_lead += ldb;
             if constexpr (!FULL) {
-                ldk_buf<K, T, false>(rsx, voff, so_glead, b[1]);
-                ldk_buf<K, T, false>(rsx, voff, so_lag, b[2]);
+                ldk_buf<K, T>(rsx, voff, so_glead, b[1]);
+                ldk_buf<K, T>(rsx, voff, so_lag, b[2]);
                 so_glead += ldb;
                 so_lag += ldb;
             }
@@ -827,7 +806,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             uint32_t so = (uint32_t)(hr - hw) * ldb;  // row r0-hw-1
             for (int i = 0; i < D - 1; ++i) {         // rows r0-hw-1 .. r0+hw-1
                 T v[K];
-                ldk_buf<K, T, false>(rsx, voff, so, v);
+                ldk_buf<K, T>(rsx, voff, so, v);
                 T *p = ring_at(sl);
 #pragma unroll
                 for (int k = 0; k < K; ++k) p[k] = v[k];
@@ -1009,9 +988,7 @@ __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_
 // One wave per workgroup; dynamic LDS per wave: the two prefix rows
 // (2*K*64 doubles), then the ring of args.ring_rows rows of 64*K values.
 // Mode of one work unit (see fused_unit) and its run.
-// UA: the map's rows are not 16-byte aligned (its own kernel, so that the
-// element-load variants do not crowd the register allocation of the others).
-template <int K, typename T, bool OUT, bool UA>
+template <int K, typename T, bool OUT>
 __device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk, double *qo, double *qi, void *ring,
                                          int ring_bytes, int lane)
 {
@@ -1032,9 +1009,9 @@ __device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk
     const bool edge_ok = F >= K && ((F - cs) % K == 0 || cs + W <= F) && left_ok;
     T *rg = (T *)ring;
     if (halo_ok && inside) {
-        fused_unit<K, T, UA ? (kFast | kElem) : kFast, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
+        fused_unit<K, T, kFast, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
     } else if (halo_ok && edge_ok) {
-        fused_unit<K, T, UA ? (kEdge | kElem) : kEdge, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
+        fused_unit<K, T, kEdge, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
     } else {
         fused_unit<K, T, kGeneral, OUT>(d, strip, rchunk, strip * d.tw - d.halo_f, qo, qi, rg, ring_bytes, lane);
     }
@@ -1045,7 +1022,7 @@ __device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk
 #endif
 // Waves per SIMD the register allocation aims at, by bytes per lane and row
 // (the LDS of one wave is small, so registers set the occupancy).
-template <int KS, typename T, bool OUT, bool UA>
+template <int KS, typename T, bool OUT>
 constexpr int fused_waves()
 {
     return KS == 8 ? 1 : sizeof(T) == 4 ? (OUT ? 2 : CFAR_WAVES_16B) : (OUT ? 1 : 2);
@@ -1054,8 +1031,8 @@ constexpr int fused_waves()
 // One wave per workgroup; dynamic LDS per wave: the two prefix rows
 // (2*kmax*64 doubles), then the ring of args.ring_bytes.  KS = 24: each
 // unit runs with its map's k (2 or 4); KS = 8: k = 8.
-template <int KS, typename T, bool OUT, bool UA>
-__global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(fused_waves<KS, T, OUT, UA>())))
+template <int KS, typename T, bool OUT>
+__global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(fused_waves<KS, T, OUT>())))
 fused_kernel(FusedArgs args)
 {
     constexpr int KM = KS == 8 ? 8 : 4;
@@ -1086,45 +1063,42 @@ fused_kernel(FusedArgs args)
         const int strip = (int)(local % (uint32_t)d.n_strips);
         const int rchunk = (int)(local / (uint32_t)d.n_strips);
         if constexpr (KS == 8) {
-            run_unit<8, T, OUT, UA>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
+            run_unit<8, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
         } else {
             if (d.k_cols == 2)
-                run_unit<2, T, OUT, UA>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
+                run_unit<2, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
             else
-                run_unit<4, T, OUT, UA>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
+                run_unit<4, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
         }
     }
 }
 
 #define CFAR_FUSED_VARIANTS(X_)                                                                        \
-    X_(24, float, false, false) X_(24, float, true, false) X_(24, double, false, false)                  \
-    X_(24, double, true, false) X_(8, float, false, false) X_(8, float, true, false)                    \
-    X_(8, double, false, false) X_(8, double, true, false) X_(24, float, false, true)                    \
-    X_(24, float, true, true) X_(24, double, false, true) X_(24, double, true, true)                    \
-    X_(8, float, false, true) X_(8, float, true, true) X_(8, double, false, true) X_(8, double, true, true)
+    X_(24, float, false) X_(24, float, true) X_(24, double, false) X_(24, double, true)                 \
+    X_(8, float, false) X_(8, float, true) X_(8, double, false) X_(8, double, true)
 
-static const void *fused_fn(int kset, int dtype, bool out, bool ua)
+static const void *fused_fn(int kset, int dtype, bool out)
 {
-#define CFAR_PICK(K_, T_, O_, U_)                                                    \
-    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_ && ua == U_) \
-        return (const void *)fused_kernel<K_, T_, O_, U_>;
+#define CFAR_PICK(K_, T_, O_)                                             \
+    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) \
+        return (const void *)fused_kernel<K_, T_, O_>;
     CFAR_FUSED_VARIANTS(CFAR_PICK)
 #undef CFAR_PICK
     return nullptr;
 }
 
-int fused_resident_blocks(int kset, int dtype, bool out, bool ua, int ring_bytes)
+int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes)
 {
     // cache: device x kernel x ring size (in 512-byte steps)
     constexpr int kSteps = 129;
-    static int cached[16][16][kSteps] = {{{0}}};
+    static int cached[16][8][kSteps] = {{{0}}};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
-    const int slot = (((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0)) * 2 + (ua ? 1 : 0);
+    const int slot = ((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0);
     const int step = ring_bytes % 512 == 0 && ring_bytes / 512 < kSteps ? ring_bytes / 512 : -1;
     int *c = dev < 16 && step >= 0 ? &cached[dev][slot][step] : nullptr;
     if (c && *c > 0) return *c;
-    const void *fn = fused_fn(kset, dtype, out, ua);
+    const void *fn = fused_fn(kset, dtype, out);
     int per_cu = 0, cus = 0;
     if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFusedThreads,
                                                             fused_lds_bytes(kset, ring_bytes)) != hipSuccess ||
@@ -1137,17 +1111,17 @@ int fused_resident_blocks(int kset, int dtype, bool out, bool ua, int ring_bytes
     return per_cu * cus;
 }
 
-hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, bool ua, hipStream_t stream)
+hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, hipStream_t stream)
 {
-    const int resident = fused_resident_blocks(kset, dtype, out, ua, args.ring_bytes);
+    const int resident = fused_resident_blocks(kset, dtype, out, args.ring_bytes);
     uint32_t blocks = args.total_units;
     if (blocks > (uint32_t)resident) blocks = (uint32_t)resident;
     if (blocks == 0) blocks = 1;
     const size_t lds = fused_lds_bytes(kset, args.ring_bytes);
-#define CFAR_LAUNCH(K_, T_, O_, U_)                                                                                \
-    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_ && ua == U_) {                               \
-        hipLaunchKernelGGL((fused_kernel<K_, T_, O_, U_>), dim3(blocks), dim3(kFusedThreads), lds, stream, args); \
-        return hipGetLastError();                                                                                  \
+#define CFAR_LAUNCH(K_, T_, O_)                                                                                \
+    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) {                                       \
+        hipLaunchKernelGGL((fused_kernel<K_, T_, O_>), dim3(blocks), dim3(kFusedThreads), lds, stream, args); \
+        return hipGetLastError();                                                                              \
     }
     CFAR_FUSED_VARIANTS(CFAR_LAUNCH)
 #undef CFAR_LAUNCH
