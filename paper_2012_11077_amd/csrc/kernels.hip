@@ -816,9 +816,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
         }
         // running slots: rows r+hw (written), r, and for FULL r+gr, r-gr-1
         int s_w = (r0 + hw) % D, s_c = r0 % D, s_g = (r0 + gr) % D, s_gl = (r0 - gr - 1 + D) % D;
-        CFAR_GLOBAL uint8_t *mptr = gbl_w(d.mask) + (int64_t)r0 * d.ld_mask + c_lane;  // stored only where lane_any_out
-        const int64_t mstep = d.ld_mask;
-        // FAST: the mask rows r0..r1-1 through a buffer resource too; a lane
+        // The mask rows r0..r1-1 through a buffer resource too; a lane
         // without output columns stores past its end, where the store is
         // dropped, so the store needs no branch (and no alignment: the
         // packed store of a lane may straddle dwords)
@@ -829,7 +827,11 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
                                                              (uint32_t)F);
         const __amdgpu_buffer_rsrc_t rsm = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(uintptr_t)(((uint64_t)mb_hi << 32) | mb_lo), (short)0, mext, kBufferFlags);
-        const uint32_t moff = lane_any_out ? (uint32_t)c_lane : 0x80000000u;
+        // (EDGE: a lane of a right-aligned last strip may own only its last
+        // K - k_own0 columns; it stores those as bytes, the packed store
+        // skips it)
+        const uint32_t moff = lane_any_out && k_own0 == 0 ? (uint32_t)c_lane : 0x80000000u;
+        const bool unit_partial = BM == kEdge && __ballot(lane_any_out && k_own0 > 0) != 0ull;
         const uint32_t mstep_u = __builtin_amdgcn_readfirstlane((uint32_t)d.ld_mask);
         uint32_t so_m = 0;
         auto next = [&](int v) { return v + 1 == D ? 0 : v + 1; };
@@ -886,21 +888,23 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             publish();
             uint32_t bits[(K + 3) / 4];
             decide_fast(xc, bits);
-            if constexpr (BM == kFast) {
-                if constexpr (K == 2) {
-                    __builtin_amdgcn_raw_buffer_store_b16((uint16_t)bits[0], rsm, moff, so_m, 0);
-                } else if constexpr (K == 4) {
-                    __builtin_amdgcn_raw_buffer_store_b32(bits[0], rsm, moff, so_m, 0);
-                } else {
-                    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-                    const u32x2 w = {bits[0], bits[1]};
-                    __builtin_amdgcn_raw_buffer_store_b64(w, rsm, moff, so_m, 0);
-                }
-                so_m += mstep_u;
+            if constexpr (K == 2) {
+                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)bits[0], rsm, moff, so_m, 0);
+            } else if constexpr (K == 4) {
+                __builtin_amdgcn_raw_buffer_store_b32(bits[0], rsm, moff, so_m, 0);
             } else {
-                if (lane_any_out) store_bits(mptr, bits);
-                mptr += mstep;
+                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+                const u32x2 w = {bits[0], bits[1]};
+                __builtin_amdgcn_raw_buffer_store_b64(w, rsm, moff, so_m, 0);
             }
+            if (unit_partial) {  // wave-uniform
+                const uint32_t pboff = lane_any_out && k_own0 > 0 ? (uint32_t)c_lane : 0x80000000u;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bits[k / 4] >> (8 * (k % 4))), rsm,
+                                                         k >= k_own0 ? pboff + (uint32_t)k : 0x80000000u, so_m, 0);
+            }
+            so_m += mstep_u;
         };
         T buf[PD][NL][K];
         int r = r0;
