@@ -212,13 +212,6 @@ static bool plan_valid(const cfar_map *m, const cfar_plan *p)
     return plan_geometry(m, p->k_cols, p->rows_per_unit, &g);
 }
 
-// Rows of map m are 16-byte aligned (vector loads).
-static bool rows_aligned(const cfar_map *m)
-{
-    const size_t es = m->dtype == CFAR_F32 ? 4 : 8;
-    return ((uintptr_t)m->x % 16 == 0) && ((m->ld * (int64_t)es) % 16 == 0);
-}
-
 // ---------------------------------------------------------------------------
 // Descriptors
 // ---------------------------------------------------------------------------
@@ -250,12 +243,11 @@ static MapDesc make_desc(const cfar_map *m, const Plan *p, double *lut)
         d.n_strips = p->n_strips;
         d.n_rchunks = p->n_rchunks;
         const size_t es = m->dtype == CFAR_F32 ? 4 : 8;
-        const bool x_vec = rows_aligned(m);
         const bool m_vec = ((uintptr_t)m->mask % 4 == 0) && (m->ld_mask % 4 == 0);
         // bit 4: the rows one work unit reads span fewer than 2^31 bytes, so
         // the interior loop can address them through one buffer resource
         const double span = ((double)p->rs + 2.0 * d.hr + 2.0) * std::max((double)m->ld * (double)es, (double)m->ld_mask);
-        d.vec_ok = (x_vec ? 1 : 0) | (m_vec ? 2 : 0) | (span < 2147483647.0 ? 4 : 0);
+        d.vec_ok = (m_vec ? 2 : 0) | (span < 2147483647.0 ? 4 : 0);
     }
     return d;
 }

@@ -35,7 +35,7 @@ struct MapDesc {
     int32_t n_strips;     // TILED: strips across the columns
     int32_t n_rchunks;    // TILED: row chunks
     int32_t n_full;       // training cells of an unclipped window
-    int32_t vec_ok;       // bits: 1 x rows 16-byte aligned (not needed by the loads), 2 mask rows aligned, 4 unit row span < 2^31 bytes
+    int32_t vec_ok;       // bits: 2 mask rows 4-byte aligned, 4 unit row span < 2^31 bytes (bit 1 unused)
     int32_t pad0;
 };
 static_assert(sizeof(MapDesc) == 128, "MapDesc must stay 128 bytes");

@@ -21,6 +21,11 @@
 //       prefix of those column sums gives the four column corners as
 //       differences read back from LDS.  The integral image itself is never
 //       written; one pass over X.
+//   stencil_direct
+//       DIRECT form (the comparison route of Table I): every cell sums its
+//       own training cells from an LDS tile, no integral image.
+// (Detection lists and packed masks are in detections.hip, the map built
+// from a raw record in mapbuild.hip.)
 #include "internal.h"
 
 #include <cmath>
