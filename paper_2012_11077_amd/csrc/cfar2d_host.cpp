@@ -177,7 +177,10 @@ static cfar_plan default_plan(const cfar_map *m)
     }
     cfar_plan out;
     out.k_cols = bk;
-    out.rows_per_unit = (int)std::min<int64_t>(64, m->rows);
+    // tall maps: longer units spread the warm-up rows (2 hr + 1 per unit)
+    // over more output rows; the rest keep short units, which also keep the
+    // end of a batched launch short (its maps run largest first)
+    out.rows_per_unit = (int)std::min<int64_t>(m->rows >= 1024 ? 128 : 64, m->rows);
     out.ring_bytes = -1;
     return out;
 }
