@@ -32,7 +32,9 @@ def declared_functions():
 def test_header_declares_the_expected_entry_points():
     names = declared_functions()
     for n in ("sat2d", "cfar2d", "cfar2d_batched", "cfar_submit", "cfar_poll", "cfar_server_create",
-              "cfar_server_destroy", "cfar_workspace_bytes", "cfar_plan_for", "cfar_last_error"):
+              "cfar_server_destroy", "cfar_workspace_bytes", "cfar_plan_for", "cfar_last_error",
+              "cfar_detections", "cfar_detections_workspace_bytes", "cfar_mask_pack", "cfar_map_build",
+              "cfar_map_bins", "cfar_map_build_workspace_bytes"):
         assert n in names
 
 

@@ -83,3 +83,17 @@ def test_direct_large_map_sampled():
     ri, ci = torch.from_numpy(rows).to(DEV), torch.from_numpy(cols).to(DEV)
     r = check_cells(x_np, spec.window, rows, cols, mask[ri, ci].cpu().numpy(), st[ri, ci].cpu().numpy(), "direct")
     say("direct 8192^2", r)
+
+
+@pytest.mark.parametrize("dtype, g, t", [("f64", 4, 24), ("f32", 2, 46), ("f64", 0, 1)])
+def test_direct_lds_limits(dtype, g, t):
+    """Windows near the form's LDS bound ((4 + 2 hr)(64 + 2 hf) x element size
+    <= 64 KiB: 57600 bytes for FP64 at hr = hf = 28, 64000 bytes for FP32 at
+    48) and the smallest one, with ragged map edges."""
+    spec = synth.MapSpec(131, 397, dtype, "exp", 1.5, n_targets=6, guard_r=g, guard_f=g, train_r=t, train_f=t,
+                         pfa=1e-3, seed=(64, g, t))
+    x_np = synth.generate(spec)
+    x = torch.from_numpy(x_np).to(DEV)
+    say("direct limits", dtype, g, t)
+    m, st, th = _run(x, spec.window, C.DIRECT)
+    check_full(x_np, spec.window, m, st, th, "direct")
