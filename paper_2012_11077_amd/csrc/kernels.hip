@@ -805,16 +805,44 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
                 so_lag += ldb;
             }
         };
-        auto ring_at = [&](int slot) -> T * { return ring + (slot * 64 + lane) * K; };
+        // a lane's K values of one ring row, moved as 16-byte LDS accesses
+        // where K * sizeof(T) is a multiple of 16 (aligned: the ring starts on
+        // a 4 KiB boundary), conflict-free at that lane stride
+        typedef uint32_t r32x4 __attribute__((ext_vector_type(4)));
+        auto ring_put = [&](int slot, const T(&v)[K]) {
+            char *p = (char *)(ring + (slot * 64 + lane) * K);
+            if constexpr (K * sizeof(T) % 16 == 0) {
+#pragma unroll
+                for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q) {
+                    r32x4 w;
+                    __builtin_memcpy(&w, (const char *)v + 16 * q, 16);
+                    *(r32x4 *)(p + 16 * q) = w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) ((T *)p)[k] = v[k];
+            }
+        };
+        auto ring_get = [&](int slot, T(&v)[K]) {
+            const char *p = (const char *)(ring + (slot * 64 + lane) * K);
+            if constexpr (K * sizeof(T) % 16 == 0) {
+#pragma unroll
+                for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q) {
+                    const r32x4 w = *(const r32x4 *)(p + 16 * q);
+                    __builtin_memcpy((char *)v + 16 * q, &w, 16);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) v[k] = ((const T *)p)[k];
+            }
+        };
         {
             int sl = (r0 - hw - 1) % D;
             uint32_t so = (uint32_t)(hr - hw) * ldb;  // row r0-hw-1
             for (int i = 0; i < D - 1; ++i) {         // rows r0-hw-1 .. r0+hw-1
                 T v[K];
                 ldk_buf<K, T>(rsx, voff, so, v);
-                T *p = ring_at(sl);
-#pragma unroll
-                for (int k = 0; k < K; ++k) p[k] = v[k];
+                ring_put(sl, v);
                 so += ldb;
                 sl = sl + 1 == D ? 0 : sl + 1;
             }
@@ -844,28 +872,15 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             T gle[K], gla[K], la[K], xc[K];
             const int s_l = next(s_w);  // row r-hw-1 = r+hw+1 mod D
             {
-                T *pw = ring_at(s_w);
-#pragma unroll
-                for (int k = 0; k < K; ++k) pw[k] = FULL ? b[0][k] : b[NL - 2][k];
-                const T *pl = ring_at(s_l);
-                const T *pc = ring_at(s_c);
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if constexpr (FULL) {
-                        la[k] = pl[k];
-                    } else {
-                        gla[k] = pl[k];
-                    }
-                    xc[k] = pc[k];
-                }
+                ring_put(s_w, b[FULL ? 0 : NL - 2]);
+                if constexpr (FULL)
+                    ring_get(s_l, la);
+                else
+                    ring_get(s_l, gla);
+                ring_get(s_c, xc);
                 if constexpr (FULL) {
-                    const T *pg = ring_at(s_g);
-                    const T *pgl = ring_at(s_gl);
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        gle[k] = pg[k];
-                        gla[k] = pgl[k];
-                    }
+                    ring_get(s_g, gle);
+                    ring_get(s_gl, gla);
                 } else {
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
