@@ -71,6 +71,32 @@ __device__ __forceinline__ double wave_incl_scan(double v)
     return v;
 }
 
+// dpp_f64 into `old`: lanes of rows that ROW_MASK leaves out keep old's value.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64_into(double old, double v)
+{
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+    int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// wave_incl_scan for a loop: z15 and z31 are carried from call to call (0.0
+// before the first); the rows their broadcast steps leave out stay zero in
+// them, so those steps need no zeroed register each time.
+__device__ __forceinline__ double wave_incl_scan_carried(double v, double &z15, double &z31)
+{
+    v += dpp_f64<dpp::kRowShr1>(v);
+    v += dpp_f64<dpp::kRowShr2>(v);
+    v += dpp_f64<dpp::kRowShr4>(v);
+    v += dpp_f64<dpp::kRowShr8>(v);
+    z15 = dpp_f64_into<dpp::kRowBcast15, 0xa>(z15, v);
+    v += z15;
+    z31 = dpp_f64_into<dpp::kRowBcast31, 0xc>(z31, v);
+    v += z31;
+    return v;
+}
+
 // Value of the previous lane (0 for lane 0).
 __device__ __forceinline__ double wave_shift_up1(double v) { return dpp_f64<dpp::kWaveShr1>(v); }
 
@@ -622,6 +648,7 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
     // then a DPP scan over the lanes), published in LDS: the row corners of
     // eq. (4) are in the column sums, the column corners are read back at
     // offsets +-h.
+    double z15o = 0.0, z31o = 0.0, z15i = 0.0, z31i = 0.0;  // see wave_incl_scan_carried
     auto publish = [&]() {
         double po[K], pi[K];
         po[0] = Co[0];
@@ -631,8 +658,8 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             po[k] = po[k - 1] + Co[k];
             pi[k] = pi[k - 1] + Ci[k];
         }
-        const double eo = wave_shift_up1(wave_incl_scan(po[K - 1]));
-        const double ei = wave_shift_up1(wave_incl_scan(pi[K - 1]));
+        const double eo = wave_shift_up1(wave_incl_scan_carried(po[K - 1], z15o, z31o));
+        const double ei = wave_shift_up1(wave_incl_scan_carried(pi[K - 1], z15i, z31i));
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
