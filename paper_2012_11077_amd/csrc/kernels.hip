@@ -658,8 +658,9 @@ __device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, doub
             po[k] = po[k - 1] + Co[k];
             pi[k] = pi[k - 1] + Ci[k];
         }
-        const double eo = wave_shift_up1(wave_incl_scan_carried(po[K - 1], z15o, z31o));
-        const double ei = wave_shift_up1(wave_incl_scan_carried(pi[K - 1], z15i, z31i));
+        // exclusive prefix of the lane totals: the inclusive one minus the lane's own
+        const double eo = wave_incl_scan_carried(po[K - 1], z15o, z31o) - po[K - 1];
+        const double ei = wave_incl_scan_carried(pi[K - 1], z15i, z31i) - pi[K - 1];
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
