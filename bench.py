@@ -294,12 +294,13 @@ def mapbuild_bench(steps=10, warmup=2):
             "note": "times include allocations of the map and workspace by the Python binding"}
 
 
-def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
+def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0, packed=False):
     """The serving workload: n_streams simulated drone streams, each emitting
     frames of its own fixed size at Poisson rate 50 Hz, submitted from
     page-locked host memory (cfar_host_alloc) to the library's server (continuous batching over 4 HIP
     streams, admission by device memory); latency is frame arrival (its
-    scheduled Poisson time) to the mask back in host memory."""
+    scheduled Poisson time) to the mask back in host memory (packed: the
+    bit-packed mask, an eighth of the bytes)."""
     import threading
     import torch
     from paper_2012_11077_amd import cfar2d as C
@@ -316,7 +317,8 @@ def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
             x.copy_(torch.from_numpy(synth.generate(sp)))
             fr.append((x, sp.window, sp.cells))
         frames.append(fr)
-        free_masks.append([C.host_empty((st["rows"], st["cols"]), torch.uint8) for _ in range(masks_per_stream)])
+        shape = (st["rows"], (st["cols"] + 31) // 32) if packed else (st["rows"], st["cols"])
+        free_masks.append([C.host_empty(shape, torch.int32 if packed else torch.uint8) for _ in range(masks_per_stream)])
     # merged Poisson arrival schedule
     arrivals = []
     for k, st in enumerate(streams):
@@ -386,7 +388,7 @@ def serve_bench(seconds, seed=4, n_streams=16, log_every=5.0):
     st = srv.stats()
     srv.close()
     wall = (t_end - t0) / 1e9
-    return {"seconds": round(wall, 2), "streams": n_streams, "rate_hz_per_stream": 50.0,
+    return {"seconds": round(wall, 2), "streams": n_streams, "rate_hz_per_stream": 50.0, "packed_masks": packed,
             "frame_sizes": "%dx%d .. %dx%d FP32" % (streams[0]["rows"], streams[0]["cols"], streams[-1]["rows"],
                                                    streams[-1]["cols"]),
             "frames": len(lat_ms), "failed": int(st.failed), "batches": int(st.batches),
@@ -573,11 +575,13 @@ def main():
                  "mask_cells_differing_from_tiled": diff}
         log("plain: %.3f ms/step (%d mask cells differ from tiled)" % (pms, diff))
 
-    serving = None
+    serving = serving_packed = None
     if args.serve_seconds > 0:
         log("serving run, %.0f s" % args.serve_seconds)
         serving = serve_bench(args.serve_seconds)
         log("serving: p50 %s ms, p99 %s ms, %d frames" % (serving["p50_ms"], serving["p99_ms"], serving["frames"]))
+        serving_packed = serve_bench(args.serve_seconds, packed=True)
+        log("serving, packed masks: p50 %s ms, p99 %s ms" % (serving_packed["p50_ms"], serving_packed["p99_ms"]))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -608,6 +612,7 @@ def main():
         "launch_latency_ms": {"p50": round(percentile(step_ms, 50), 4), "p99": round(percentile(step_ms, 99), 4),
                               "what": "per batched launch, back-to-back"},
         "serving": serving,
+        "serving_packed_masks": serving_packed,
         "plain_form": plain,
         "speedup_vs_plain": (round(plain["ms_per_step"] / ms_per_step, 3) if plain else None),
         "effective_hbm_frac": round((in_bytes + cells) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -245,14 +245,23 @@ int cfar_host_free(void *p);
  * to the free device memory) and starts its scheduler thread. */
 int cfar_server_create(const cfar_server_opts *opts, cfar_server **out);
 
-/* Submit one frame (TILED form, FP32 or FP64).  x_on_host = 1: frame->x and
- * frame->mask are HOST pointers (pinned memory gives overlap); the server
- * copies X in and the mask out, and train_sum/threshold must be NULL.
- * x_on_host = 0: all pointers are device pointers.  Buffers must stay valid
- * until the ticket completes.  Never blocks: CFAR_EAGAIN when the queue is
- * full, CFAR_EINVAL for a bad frame or one larger than the device budget,
- * CFAR_ESHUTDOWN after destroy began. */
-int cfar_submit(cfar_server *s, const cfar_map *frame, int32_t x_on_host, uint64_t user_tag,
+/* Submit flags. */
+enum {
+    CFAR_SUBMIT_HOST = 1,        /* frame->x and frame->mask are host pointers               */
+    CFAR_SUBMIT_PACKED_MASK = 2  /* with CFAR_SUBMIT_HOST: frame->mask receives the bit-packed
+                                    mask (as cfar_mask_pack: rows x ld_mask uint32 words,
+                                    ld_mask >= ceil(cols / 32)), an eighth of the bytes */
+};
+
+/* Submit one frame (TILED form, FP32 or FP64).  flags & CFAR_SUBMIT_HOST:
+ * frame->x and frame->mask are HOST pointers (pinned memory gives overlap);
+ * the server copies X in and the mask out (packed on the device first with
+ * CFAR_SUBMIT_PACKED_MASK), and train_sum/threshold must be NULL.  Without
+ * it all pointers are device pointers (flags 0; 1 is the former x_on_host =
+ * 1).  Buffers must stay valid until the ticket completes.  Never blocks:
+ * CFAR_EAGAIN when the queue is full, CFAR_EINVAL for a bad frame or flags or
+ * one larger than the device budget, CFAR_ESHUTDOWN after destroy began. */
+int cfar_submit(cfar_server *s, const cfar_map *frame, int32_t flags, uint64_t user_tag,
                 uint64_t *ticket_out);
 
 /* Collect up to `max` completions, waiting up to timeout_us (0 = do not

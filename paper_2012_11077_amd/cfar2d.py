@@ -28,6 +28,7 @@ CFAR_OK, CFAR_EINVAL, CFAR_ENOSPC, CFAR_EDEVICE, CFAR_EAGAIN, CFAR_ESHUTDOWN = 0
 F32, F64 = 0, 1
 PLAIN, TILED, DIRECT = 0, 1, 2
 BATCH_GRAPH = 1
+SUBMIT_HOST, SUBMIT_PACKED_MASK = 1, 2
 STATUS_NAMES = {0: "CFAR_OK", -1: "CFAR_EINVAL", -2: "CFAR_ENOSPC", -3: "CFAR_EDEVICE",
                 -4: "CFAR_EAGAIN", -5: "CFAR_ESHUTDOWN"}
 
@@ -432,7 +433,8 @@ def host_empty(shape, dtype=torch.float32) -> torch.Tensor:
     every view of it are gone."""
     import weakref
     import numpy as np
-    np_dtype = {torch.float32: np.float32, torch.float64: np.float64, torch.uint8: np.uint8}[dtype]
+    np_dtype = {torch.float32: np.float32, torch.float64: np.float64, torch.uint8: np.uint8,
+                torch.int32: np.int32}[dtype]
     n = 1
     for d in shape:
         n *= int(d)
@@ -461,13 +463,27 @@ class Server:
     def submit(self, x: torch.Tensor, window, mask: torch.Tensor, tag: int = 0, train_sum=None,
                threshold=None) -> Optional[int]:
         """Ticket of the submitted frame, or None when the queue is full
-        (CFAR_EAGAIN).  Other errors raise."""
+        (CFAR_EAGAIN).  Other errors raise.  A host frame's mask may be an
+        int32 tensor of rows x ceil(cols/32) words: it then receives the
+        bit-packed mask (cell (r, 32 w + u) at bit u of word w)."""
         on_host = x.device.type == "cpu"
         if (mask.device.type == "cpu") != on_host:
             raise ValueError("x and mask must both be on the host or both on the device")
-        m = make_map(x, window, mask, train_sum, threshold)
+        flags = SUBMIT_HOST if on_host else 0
+        if mask.dtype == torch.int32:
+            _check_2d(x, "x")
+            _check_2d(mask, "mask")
+            R, F = x.shape
+            if mask.size(0) != R or mask.size(1) < (F + 31) // 32:
+                raise ValueError("packed mask must be rows x ceil(cols/32) words")
+            w = window if isinstance(window, Window) else make_window(*window)
+            m = Map(x.data_ptr(), _dtype_code(x), 0, R, F, x.stride(0) if R > 1 else F, w, mask.data_ptr(),
+                    mask.stride(0) if R > 1 else mask.size(1), None, None)
+            flags |= SUBMIT_PACKED_MASK
+        else:
+            m = make_map(x, window, mask, train_sum, threshold)
         t = ctypes.c_uint64()
-        rc = lib().cfar_submit(self._h, ctypes.byref(m), 1 if on_host else 0, int(tag), ctypes.byref(t))
+        rc = lib().cfar_submit(self._h, ctypes.byref(m), flags, int(tag), ctypes.byref(t))
         if rc == CFAR_EAGAIN:
             return None
         _check(rc)

@@ -98,6 +98,7 @@ private:
 struct Frame {
     cfar_map map;       // as submitted (host or device pointers)
     bool on_host;
+    bool packed;        // the host mask takes the bit-packed mask (rows x ld_mask words)
     uint64_t ticket, tag;
     int64_t t_submit, t_start;
     size_t off_x = 0, off_m = 0, bytes_x = 0, bytes_m = 0;  // pool blocks of host frames
@@ -163,11 +164,17 @@ void post(cfar_server *s, const Frame &f, int status, int64_t t_done)
 size_t frame_es(const cfar_map &m) { return m.dtype == CFAR_F32 ? 4 : 8; }
 
 // Pool bytes a frame holds while in flight.
+// Words per row of a packed mask.
+int64_t packed_words(const cfar_map &m) { return (m.cols + 31) / 32; }
+
+// Pool bytes a frame holds while in flight: its map and its mask (and the
+// packed mask after the mask, 256-byte aligned, for packed frames).
 void frame_bytes(const Frame &f, size_t *bx, size_t *bm)
 {
     if (!f.on_host) { *bx = *bm = 0; return; }
     *bx = (size_t)f.map.rows * (size_t)f.map.cols * frame_es(f.map);
     *bm = (size_t)f.map.rows * (size_t)f.map.cols;
+    if (f.packed) *bm = align_up(*bm, 256) + (size_t)f.map.rows * (size_t)packed_words(f.map) * 4;
 }
 
 // Reap finished batches (lock held).
@@ -228,6 +235,20 @@ int launch(cfar_server *s, Batch &b)
     for (size_t i = 0; i < b.frames.size(); ++i) {
         const Frame &f = b.frames[i];
         if (!f.on_host) continue;
+        if (f.packed) {  // pack on the device, copy the words back
+            const int64_t words = packed_words(f.map);
+            uint32_t *dp = (uint32_t *)(s->pool_base + f.off_m +
+                                        align_up((size_t)f.map.rows * (size_t)f.map.cols, 256));
+            int prc = cfar_mask_pack(&maps[i], dp, words, st);
+            if (prc != CFAR_OK) return prc;
+            hipError_t e = f.map.ld_mask == words
+                               ? hipMemcpyAsync(f.map.mask, dp, (size_t)f.map.rows * (size_t)words * 4,
+                                                hipMemcpyDeviceToHost, st)
+                               : hipMemcpy2DAsync(f.map.mask, (size_t)f.map.ld_mask * 4, dp, (size_t)words * 4,
+                                                  (size_t)words * 4, (size_t)f.map.rows, hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return hip_error(e, "hipMemcpy2DAsync(packed mask out)");
+            continue;
+        }
         hipError_t e = f.map.ld_mask == f.map.cols
                            ? hipMemcpyAsync(f.map.mask, maps[i].mask, (size_t)f.map.rows * (size_t)f.map.cols,
                                             hipMemcpyDeviceToHost, st)
@@ -455,20 +476,30 @@ int cfar_server_create(const cfar_server_opts *opts, cfar_server **out)
     return CFAR_OK;
 }
 
-int cfar_submit(cfar_server *s, const cfar_map *frame, int32_t x_on_host, uint64_t user_tag, uint64_t *ticket_out)
+int cfar_submit(cfar_server *s, const cfar_map *frame, int32_t flags, uint64_t user_tag, uint64_t *ticket_out)
 {
     if (!s || !frame || !ticket_out) return set_error(CFAR_EINVAL, "server, frame or ticket_out is NULL");
-    int rc = validate_map(frame, 0, CFAR_FORM_TILED);
+    if (flags & ~(CFAR_SUBMIT_HOST | CFAR_SUBMIT_PACKED_MASK)) return set_error(CFAR_EINVAL, "unknown flags 0x%x", flags);
+    const bool on_host = (flags & CFAR_SUBMIT_HOST) != 0, packed = (flags & CFAR_SUBMIT_PACKED_MASK) != 0;
+    if (packed && !on_host) return set_error(CFAR_EINVAL, "CFAR_SUBMIT_PACKED_MASK needs CFAR_SUBMIT_HOST");
+    cfar_map v = *frame;
+    if (packed) {  // ld_mask counts 32-bit words; the device-side mask is dense
+        if (frame->ld_mask < packed_words(*frame) || frame->ld_mask < 1)
+            return set_error(CFAR_EINVAL, "packed mask: ld_mask (words) < ceil(cols / 32)");
+        v.ld_mask = v.cols;
+    }
+    int rc = validate_map(&v, 0, CFAR_FORM_TILED);
     if (rc != CFAR_OK) return rc;
-    if (x_on_host && (frame->train_sum || frame->threshold))
+    if (on_host && (frame->train_sum || frame->threshold))
         return set_error(CFAR_EINVAL, "frames from host memory take no training-sum or threshold output");
     Frame f;
     f.map = *frame;
-    f.on_host = x_on_host != 0;
+    f.on_host = on_host;
+    f.packed = packed;
     f.tag = user_tag;
     size_t bx, bm;
     frame_bytes(f, &bx, &bm);
-    const size_t ws = cfar_workspace_bytes(frame, 1, CFAR_FORM_TILED);
+    const size_t ws = cfar_workspace_bytes(&v, 1, CFAR_FORM_TILED);
     if (!ws) return CFAR_EINVAL;
     if (align_up(bx, kAlign) + align_up(bm, kAlign) + align_up(ws + ws / 2, kAlign) > s->pool_bytes)
         return set_error(CFAR_EINVAL, "frame needs more device memory than the server's budget");

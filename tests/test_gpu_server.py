@@ -2,6 +2,7 @@
 cfar_server_shutdown / cfar_server_destroy) on the GPU: each frame's result
 is the same alone and in the mix, back-pressure, admission by device
 memory, and both shutdown modes."""
+import ctypes
 import time
 
 import numpy as np
@@ -162,3 +163,55 @@ def test_shutdown(drain):
                 assert (keep[k][1].numpy() == 9).all()
             else:
                 assert np.array_equal(keep[k][1].numpy(), _alone(xs[k], specs[k].window))
+
+
+def test_packed_masks():
+    """Host frames submitted with packed masks (int32 words, some with a
+    padded row pitch) next to dense ones: every packed mask unpacks to the
+    frame's mask alone, padding words stay untouched; packed masks need host
+    frames, enough words per row, and known flags."""
+    specs, xs = _frames(12, seed=34, rows=(50, 700), cols=(33, 900))
+    ref = [_alone(x, s.window) for x, s in zip(xs, specs)]
+    with C.Server(device_budget_bytes=128 << 20, max_inflight_frames=8, n_hip_streams=2,
+                  queue_depth=32, max_batch_frames=4) as srv:
+        keep, tickets = [], {}
+        for k, (s, x) in enumerate(zip(specs, xs)):
+            xh = C.host_empty(x.shape, torch.from_numpy(x).dtype)
+            xh.copy_(torch.from_numpy(x))
+            if k % 3 == 2:      # dense
+                mh = C.host_empty(x.shape, torch.uint8)
+                mh.fill_(5)
+            else:               # packed, row pitch of words + (k % 3) padding words
+                words = (x.shape[1] + 31) // 32
+                buf = C.host_empty((x.shape[0], words + k % 3), torch.int32)
+                buf.fill_(-7)
+                mh = buf
+            t = None
+            while t is None:
+                t = srv.submit(xh, s.window, mh, tag=k)
+            tickets[t] = k
+            keep.append((xh, mh))
+        got = _drain(srv, tickets)
+        dev = torch.from_numpy(xs[0]).to(DEV)
+        bad = torch.zeros((xs[0].shape[0], (xs[0].shape[1] + 31) // 32), dtype=torch.int32, device=DEV)
+        with pytest.raises(C.CfarError):          # packed needs a host frame
+            srv.submit(dev, specs[0].window, bad)
+        short = C.host_empty((xs[0].shape[0], max(1, (xs[0].shape[1] + 31) // 32 - 1)), torch.int32)
+        if xs[0].shape[1] > 32:
+            with pytest.raises((C.CfarError, ValueError)):
+                srv.submit(keep[0][0], specs[0].window, short)
+        m = C.make_map(keep[2][0], specs[2].window, keep[2][1])
+        tk = ctypes.c_uint64()
+        assert C.lib().cfar_submit(srv._h, ctypes.byref(m), 4, 0, ctypes.byref(tk)) == C.CFAR_EINVAL
+    for t, c in got.items():
+        k = tickets[t]
+        assert c.status == C.CFAR_OK
+        mh = keep[k][1].numpy()
+        if mh.dtype == np.uint8:
+            assert np.array_equal(mh, ref[k])
+            continue
+        F = xs[k].shape[1]
+        words = (F + 31) // 32
+        bits = np.unpackbits(mh[:, :words].view(np.uint32).view(np.uint8), axis=1, bitorder="little")[:, :F]
+        assert np.array_equal(bits, ref[k]), k
+        assert (mh[:, words:] == -7).all()
