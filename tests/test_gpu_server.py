@@ -49,7 +49,7 @@ def test_alone_equals_in_mix():
     with C.Server(device_budget_bytes=256 << 20, max_inflight_frames=16, n_hip_streams=3,
                   queue_depth=64, max_batch_frames=6) as srv:
         keep, tickets = [], {}
-        for k, (s, x) in enumerate(zip(specs, xs)):
+        for k, x in enumerate(xs):
             if k % 4 == 0:   # host frame, page-locked by the library
                 xh = C.host_empty(x.shape, torch.from_numpy(x).dtype)
                 xh.copy_(torch.from_numpy(x))
@@ -61,12 +61,15 @@ def test_alone_equals_in_mix():
             else:            # device frame
                 xh = torch.from_numpy(x).to(DEV)
                 mh = torch.full(x.shape, 7, dtype=torch.uint8, device=DEV)
-            torch.cuda.synchronize()
+            keep.append((xh, mh))
+        torch.cuda.synchronize()
+        # every frame is ready before the first submit: they arrive together
+        # and the server batches them
+        for k, (s, (xh, mh)) in enumerate(zip(specs, keep)):
             t = None
             while t is None:
                 t = srv.submit(xh, s.window, mh, tag=k)
             tickets[t] = k
-            keep.append((xh, mh))
         say("server mix", len(tickets))
         got = _drain(srv, tickets)
         st = srv.stats()
