@@ -38,7 +38,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "CA-CFAR cells/s & % HBM peak, chosen vs plain form at equal mask; p99 latency"
 # rocprofv3 counter summaries of the fused kernel, per workload
 TRAFFIC_FILES = {"batched": os.path.join(ROOT, "profiles", "fused_kernel_uneven_batch_traffic.json"),
-                 "precision": os.path.join(ROOT, "profiles", "fused_kernel_16k_f32_map_traffic.json")}
+                 "precision": os.path.join(ROOT, "profiles", "fused_kernel_16k_f32_map_traffic.json"),
+                 "plain_scale": os.path.join(ROOT, "profiles", "fused_kernel_8k_f64_map_traffic.json")}
 
 
 def log(*a):

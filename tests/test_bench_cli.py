@@ -17,7 +17,8 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_traffic_files_are_well_formed():
-    for name in ("fused_kernel_uneven_batch_traffic.json", "fused_kernel_16k_f32_map_traffic.json"):
+    for name in ("fused_kernel_uneven_batch_traffic.json", "fused_kernel_16k_f32_map_traffic.json",
+                 "fused_kernel_8k_f64_map_traffic.json"):
         with open(os.path.join(ROOT, "profiles", name)) as f:
             t = json.load(f)
         assert t["kernel"] == "fused_kernel" and len(t["kernel_sha"]) == 16
