@@ -163,7 +163,6 @@ void post(cfar_server *s, const Frame &f, int status, int64_t t_done)
 
 size_t frame_es(const cfar_map &m) { return m.dtype == CFAR_F32 ? 4 : 8; }
 
-// Pool bytes a frame holds while in flight.
 // Words per row of a packed mask.
 int64_t packed_words(const cfar_map &m) { return (m.cols + 31) / 32; }
 
