@@ -121,6 +121,7 @@ struct Plan {
 };
 
 static int ring_budget();
+static int min_units();
 
 static bool plan_geometry(const cfar_map *m, int k, int rs, Plan *p, int ring_bytes = -1)
 {
@@ -140,6 +141,8 @@ static bool plan_geometry(const cfar_map *m, int k, int rs, Plan *p, int ring_by
     p->ring_bytes = ring_bytes >= 0 ? ring_bytes : ring_budget();
     return true;
 }
+
+static uint64_t units_of(const Plan &p) { return (uint64_t)p.n_strips * (uint64_t)p.n_rchunks; }
 
 struct PlanRule {
     int dtype;                    // -1 = any
@@ -181,6 +184,14 @@ static cfar_plan default_plan(const cfar_map *m)
     // over more output rows; the rest keep short units, which also keep the
     // end of a batched launch short (its maps run largest first)
     out.rows_per_unit = (int)std::min<int64_t>(m->rows >= 1024 ? 128 : 64, m->rows);
+    // a map of few units runs on few waves, each walking its rows in turn:
+    // shorter units (not below 16 rows) spread it over more of the chip
+    Plan g;
+    if (plan_geometry(m, bk, out.rows_per_unit, &g) && units_of(g) < (uint64_t)min_units()) {
+        const int64_t want = (m->rows * g.n_strips + min_units() - 1) / min_units();
+        const int64_t rs = std::max<int64_t>(16, (want + 7) / 8 * 8);
+        if (rs < out.rows_per_unit) out.rows_per_unit = (int)rs;
+    }
     out.ring_bytes = -1;
     return out;
 }
@@ -300,6 +311,18 @@ static int ring_budget()
     return v;
 }
 
+// Work units below which the cost model shortens a map's units
+// (CFAR2D_MIN_UNITS overrides the default, for tuning).
+static int min_units()
+{
+    static int v = -1;
+    if (v < 0) {
+        const char *e = std::getenv("CFAR2D_MIN_UNITS");
+        v = e ? std::max(0, std::atoi(e)) : kDefaultMinUnits;
+    }
+    return v;
+}
+
 // Maps of one kernel class (columns per lane k, dtype) and their work units.
 struct KClass {
     int kset, dtype;  // kset 24: maps planned with k = 2 or 4; 8: k = 8
@@ -313,7 +336,6 @@ static int class_slot(int kset, int dtype, bool out)
 }
 static bool has_outputs(const cfar_map *m) { return m->train_sum != nullptr || m->threshold != nullptr; }
 
-static uint64_t units_of(const Plan &p) { return (uint64_t)p.n_strips * (uint64_t)p.n_rchunks; }
 
 // LDS one workgroup may use on the current device (queried once).
 static int max_lds_per_block()

@@ -131,6 +131,7 @@ constexpr int kFusedThreads = 64;  // one wave per workgroup: LDS is sized per w
 constexpr int kMaxK = 8;
 constexpr int kMaxRingRows = 64;
 constexpr int kDefaultRingBytes = 12288;
+constexpr int kDefaultMinUnits = 128;
 
 inline int kset_of(int k) { return k == 8 ? 8 : 24; }
 inline int kmax_of(int kset) { return kset == 8 ? 8 : 4; }

@@ -159,8 +159,12 @@ def test_planner_follows_the_cost_model(L, builtin_model):
     assert plan(16384, 16384, (4, 4, 24, 24, 1e-5))[0] == 4      # wide map: k = 4
     assert plan(16384, 16384, (1, 1, 1, 1, 1e-5))[0] == 4
     assert plan(300, 65, (1, 1, 4, 4, 1e-3))[0] == 2             # narrow map: k = 2
-    k, rs, ring = plan(50, 4000, (1, 1, 4, 4, 1e-3))
-    assert rs == 50 and ring == -1                                # short map: one row chunk
+    k, rs, ring = plan(50, 40000, (1, 1, 4, 4, 1e-3))
+    assert rs == 50 and ring == -1                                # short wide map: one row chunk
+    # few units at 128 rows (8 row chunks x 3 strips): shorter units, so that
+    # the map spreads over at least 128 of them
+    assert plan(1024, 600, (4, 4, 8, 8, 1e-4)) == (4, 24, -1)
+    assert plan(50, 4000, (1, 1, 4, 4, 1e-3))[1] == 16            # not below 16 rows
 
 
 def test_plan_table_rules(L, tmp_path, builtin_model):
