@@ -123,23 +123,94 @@ def percentile(v, q):
     return v[k]
 
 
-def cpu_baseline(specs, arrays, budget_s=12.0):
-    """The FP64 oracle (single thread, as it stands) on the first maps of the
-    batch until about budget_s of CPU work; cells/s over that sample."""
+def oracle_threads():
+    """Host threads the all-core oracle run uses: OMP_NUM_THREADS if set (the
+    host's share), else every core."""
+    try:
+        return max(1, int(os.environ.get("OMP_NUM_THREADS", "")))
+    except ValueError:
+        return max(1, os.cpu_count() or 1)
+
+
+def cpu_baseline(specs, arrays, gpu_masks=None, reps=3):
+    """The FP64 oracle as it stands over the whole workload: one pass on one
+    thread, then the per-cell loop on all host threads (median of reps).
+    The all-thread run's masks are compared with the GPU's outside the
+    near-threshold margin (mismatches expected: none)."""
     import oracle
     oracle.build(force=False)
-    cells, t_tot, n = 0, 0.0, 0
+    cells = sum(s.cells for s in specs)
+    t0 = time.perf_counter()
     for s, x in zip(specs, arrays):
-        t0 = time.perf_counter()
-        oracle.cfar2d(x, *s.window)
-        t_tot += time.perf_counter() - t0
-        cells += s.cells
-        n += 1
-        if t_tot >= budget_s:
-            break
-    return {"value": cells / t_tot, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d maps of the workload (%d cells), oracle FP64 single thread, %.1f s"
-                      % (n, len(specs), cells, t_tot)}
+        oracle.cfar2d(x, *s.window, threads=1, counts=False)
+    t_one = time.perf_counter() - t0
+    nt = oracle_threads()
+    times, mismatch, near = [], 0, 0
+    for rep in range(reps):
+        t = 0.0
+        for k, (s, x) in enumerate(zip(specs, arrays)):
+            t0 = time.perf_counter()
+            m_o, _, _, thr_o = oracle.cfar2d(x, *s.window, threads=nt, counts=False)
+            t += time.perf_counter() - t0
+            if rep == 0 and gpu_masks is not None:
+                nr = oracle.near_threshold(x, thr_o)
+                mismatch += int(((gpu_masks[k] != m_o) & ~nr).sum())
+                near += int(nr.sum())
+        times.append(t)
+    t_all = float(np.median(times))
+    return {"value": cells / t_all, "unit": "cells/s", "cores": nt, "kind": "oracle",
+            "single_thread_cells_per_s": cells / t_one, "single_thread_s": round(t_one, 2),
+            "all_threads_s": round(t_all, 3), "all_threads_reps": reps,
+            "sample": "every map of the workload (%d maps, %d cells): FP64 oracle once on 1 thread, then its "
+                      "per-cell loop on %d threads, median of %d" % (len(specs), cells, nt, reps),
+            "gpu_vs_oracle": ({"mask_cells_differing_outside_margin": mismatch, "near_threshold_cells": near,
+                               "margin": "|X - T| <= 1e-5 |T|"} if gpu_masks is not None else None)}
+
+
+def precision_report():
+    """The precision workload (16384 x 16384 FP32, log-normal clutter, guard
+    4, training 24, Pfa 1e-5) on the benchmark's launch of the chosen form,
+    with and without the training-sum output, and on the plain FP64 form:
+    largest relative box-sum error against the FP64 oracle, near-threshold
+    cells, mask cells differing outside the margin."""
+    import torch
+    import oracle
+    from paper_2012_11077_amd import cfar2d as C
+    from paper_2012_11077_amd import synth
+    dev = torch.device("cuda:0")
+    spec = synth.config2()
+    x_np = synth.generate(spec)
+    x = torch.from_numpy(x_np).to(dev)
+    stream = torch.cuda.Stream()
+    out = {}
+    masks = {}
+    for name, form, with_st in (("chosen", C.TILED, False), ("chosen_with_sums", C.TILED, True),
+                                ("plain", C.PLAIN, True)):
+        mask = torch.empty(x.shape, dtype=torch.uint8, device=dev)
+        st = torch.empty(x.shape, dtype=torch.float64, device=dev) if with_st else None
+        b = C.Batch([x], [spec.window], form, masks=[mask], train_sums=[st] if st is not None else None)
+        for _ in range(2):
+            b.run(C.BATCH_GRAPH, stream=stream)
+        stream.synchronize()
+        masks[name] = mask.cpu().numpy()
+        out[name] = {"st": st.cpu().numpy() if st is not None else None}
+        del b, st
+    torch.cuda.synchronize()
+    m_o, st_o, _, thr_o = oracle.cfar2d(x_np, *spec.window, threads=oracle_threads(), counts=False)
+    near = oracle.near_threshold(x_np, thr_o)
+    rep = {"workload": "16384x16384 FP32, log-normal clutter sigma 2, 1000 targets 8-30 dB, guard 4x4, "
+                       "training 24x24, Pfa 1e-5, seed 2",
+           "near_threshold_cells": int(near.sum()), "oracle_detections": int(m_o.sum()),
+           "chosen_masks_equal_with_and_without_sums": bool(np.array_equal(masks["chosen"],
+                                                                           masks["chosen_with_sums"]))}
+    for name in ("chosen", "plain"):
+        rep[name + "_mask_cells_differing_outside_margin"] = int(((masks[name] != m_o) & ~near).sum())
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for name, key in (("chosen_with_sums", "chosen"), ("plain", "plain")):
+            st = out[name]["st"]
+            rel = np.where(st_o != 0, np.abs(st - st_o) / np.abs(st_o), 0.0)
+            rep[key + "_max_rel_box_sum_err"] = float(rel.max())
+    return rep
 
 
 # Table I of the paper (workstation, Intel Core i5-6200U): CA-CFAR without and
@@ -447,8 +518,12 @@ def main():
                     help="only the detection-list and packed-mask timing on the 16384^2 FP32 map")
     ap.add_argument("--table1", action="store_true",
                     help="only the Table I comparison: DIRECT vs TILED vs PLAIN per (guard, background) setting")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving run (16 Poisson streams at 50 Hz); 0 skips it")
+    ap.add_argument("--packed-serve-seconds", type=float, default=10.0,
+                    help="length of the serving run with bit-packed masks; 0 skips it")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the precision report (16384^2 FP32 map against the oracle)")
     ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the traffic file from rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
@@ -576,18 +651,27 @@ def main():
                  "mask_cells_differing_from_tiled": diff}
         log("plain: %.3f ms/step (%d mask cells differ from tiled)" % (pms, diff))
 
+    gpu_masks = [m.cpu().numpy() for m in masks]
+
     serving = serving_packed = None
     if args.serve_seconds > 0:
         log("serving run, %.0f s" % args.serve_seconds)
         serving = serve_bench(args.serve_seconds)
         log("serving: p50 %s ms, p99 %s ms, %d frames" % (serving["p50_ms"], serving["p99_ms"], serving["frames"]))
-        serving_packed = serve_bench(args.serve_seconds, packed=True)
-        log("serving, packed masks: p50 %s ms, p99 %s ms" % (serving_packed["p50_ms"], serving_packed["p99_ms"]))
+        if args.packed_serve_seconds > 0:
+            serving_packed = serve_bench(args.packed_serve_seconds, packed=True)
+            log("serving, packed masks: p50 %s ms, p99 %s ms" % (serving_packed["p50_ms"], serving_packed["p99_ms"]))
+
+    precision = None
+    if args.workload == "batched" and not args.no_precision:
+        log("precision form report (16384^2 FP32 against the oracle)")
+        precision = precision_report()
+        log("precision: %s" % json.dumps(precision))
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        cpu = cpu_baseline(specs, arrays)
+        log("cpu baseline (oracle, whole workload)")
+        cpu = cpu_baseline(specs, arrays, gpu_masks)
 
     out = {
         "metric": METRIC,
@@ -616,6 +700,7 @@ def main():
         "serving_packed_masks": serving_packed,
         "plain_form": plain,
         "speedup_vs_plain": (round(plain["ms_per_step"] / ms_per_step, 3) if plain else None),
+        "precision_form": precision,
         "effective_hbm_frac": round((in_bytes + cells) / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
     }
     print(json.dumps(out), flush=True)

@@ -184,10 +184,9 @@ int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags,
 typedef struct {
     int32_t k_cols;        /* columns per lane: 2, 4 or 8 (a 64-lane wave covers 64*k_cols cols) */
     int32_t rows_per_unit; /* output rows per work unit, 1..4096                                  */
-    int32_t ring_bytes;    /* LDS bytes per wave for the ring of recent rows, 0..65536, or -1 for
-                            * the library default.  The ring holds either every row of the
-                            * window (one global load per row) or only the guard rows (three),
-                            * whichever fits; 0 = no ring (five).  Results do not depend on it. */
+    int32_t ring_bytes;    /* 0..65536, or -1 for the library default: accepted for plan tables
+                            * written for earlier kernels, and ignored (the kernel reads every
+                            * row through its own buffer resource and keeps no row ring) */
 } cfar_plan;
 
 /* The plan the TILED form uses for map m (from the loaded table, else the
@@ -258,7 +257,10 @@ enum {
  * the server copies X in and the mask out (packed on the device first with
  * CFAR_SUBMIT_PACKED_MASK), and train_sum/threshold must be NULL.  Without
  * it all pointers are device pointers (flags 0; 1 is the former x_on_host =
- * 1).  Buffers must stay valid until the ticket completes.  Never blocks:
+ * 1); the server reads and writes them on its own HIP streams, which are not
+ * ordered after the caller's: the work that produces a device frame must be
+ * complete (synchronized) before cfar_submit, and its mask is ready when the
+ * ticket completes.  Buffers must stay valid until the ticket completes.  Never blocks:
  * CFAR_EAGAIN when the queue is full, CFAR_EINVAL for a bad frame or flags or
  * one larger than the device budget, CFAR_ESHUTDOWN after destroy began. */
 int cfar_submit(cfar_server *s, const cfar_map *frame, int32_t flags, uint64_t user_tag,

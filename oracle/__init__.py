@@ -38,10 +38,11 @@ _vp = ctypes.c_void_p
 
 
 def build(force: bool = True) -> str:
-    """Compile ``cfar_oracle.c`` into ``liboracle.so`` with gcc (-O2, no FMA contraction)."""
+    """Compile ``cfar_oracle.c`` into ``liboracle.so`` with gcc (-O2, no FMA
+    contraction; OpenMP only splits the rows of the per-cell loop)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fopenmp", "-fPIC",
                "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
@@ -59,7 +60,7 @@ def _load():
         lib.oracle_alpha.argtypes = [_i64, _dbl]
         lib.oracle_alpha.restype = _dbl
         lib.oracle_cfar2d.argtypes = [_vp, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _dbl,
-                                      _vp, _vp, _vp, _vp]
+                                      _vp, _vp, _vp, _vp, ctypes.c_int]
         lib.oracle_cfar2d.restype = ctypes.c_int
         lib.oracle_cfar2d_cells.argtypes = [_vp, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _dbl,
                                             _vp, _vp, _i64, _vp, _vp, _vp, _vp]
@@ -95,21 +96,24 @@ def alpha(n: int, pfa: float) -> float:
     return float(_load().oracle_alpha(int(n), float(pfa)))
 
 
-def cfar2d(x: np.ndarray, guard_r: int, guard_f: int, train_r: int, train_f: int, pfa: float):
+def cfar2d(x: np.ndarray, guard_r: int, guard_f: int, train_r: int, train_f: int, pfa: float,
+           threads: int = 1, counts: bool = True):
     """II CA-CFAR (eqs. 1-4) over the whole map.
 
     Returns ``(mask uint8, train_sum f64, n_train i64, threshold f64)``, each R x F.
     Windows are clipped at the border and the threshold uses the number of
-    training cells inside the map.
+    training cells inside the map.  ``threads`` > 1 runs the per-cell loop on
+    that many threads (same outputs); ``counts=False`` skips the training
+    counts (``n_train`` is then None), to save memory on large maps.
     """
     x = _as_f64(x)
     R, F = x.shape
     mask = np.empty((R, F), dtype=np.uint8)
     st = np.empty((R, F), dtype=np.float64)
-    nt = np.empty((R, F), dtype=np.int64)
+    nt = np.empty((R, F), dtype=np.int64) if counts else None
     thr = np.empty((R, F), dtype=np.float64)
     rc = _load().oracle_cfar2d(_ptr(x), R, F, F, guard_r, guard_f, train_r, train_f, float(pfa),
-                               _ptr(mask), _ptr(st), _ptr(nt), _ptr(thr))
+                               _ptr(mask), _ptr(st), _ptr(nt) if counts else None, _ptr(thr), int(threads))
     if rc != 0:
         raise MemoryError("oracle could not allocate the integral image")
     return mask, st, nt, thr

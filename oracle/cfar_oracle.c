@@ -93,11 +93,13 @@ static int decide(double cut, double st, int64_t nt, double pfa, double *thr)
  * x: R x F row-major with leading dimension ld.  Window: guard half-widths
  * gr (rows) / gf (cols), training half-widths tr / tf.  Outputs (any may be
  * NULL except mask): mask R x F (0/1), training sum, training count and
- * threshold per cell, all with leading dimension F.  Returns 0, or -1 when
- * the SAT could not be allocated. */
+ * threshold per cell, all with leading dimension F.  nthreads > 1 splits the
+ * rows of the per-cell loop over that many OpenMP threads; every cell runs
+ * the same code on the same integral image, so the outputs do not depend on
+ * it.  Returns 0, or -1 when the SAT could not be allocated. */
 int oracle_cfar2d(const double *x, int64_t R, int64_t F, int64_t ld,
                   int64_t gr, int64_t gf, int64_t tr, int64_t tf, double pfa,
-                  uint8_t *mask, double *train_sum, int64_t *n_train, double *thresh)
+                  uint8_t *mask, double *train_sum, int64_t *n_train, double *thresh, int nthreads)
 {
     const int64_t W = F + 1;
     double *S = (double *)malloc(sizeof(double) * (size_t)(R + 1) * (size_t)W);
@@ -105,6 +107,9 @@ int oracle_cfar2d(const double *x, int64_t R, int64_t F, int64_t ld,
         return -1;
     oracle_sat(x, R, F, ld, S);
     const int64_t hr = gr + tr, hf = gf + tf;
+    if (nthreads < 1)
+        nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
     for (int64_t i = 0; i < R; ++i) {
         for (int64_t j = 0; j < F; ++j) {
             /* outer (guard + training) and inner (guard, holds the CUT) rectangles, clipped */

@@ -469,6 +469,10 @@ class Server:
         on_host = x.device.type == "cpu"
         if (mask.device.type == "cpu") != on_host:
             raise ValueError("x and mask must both be on the host or both on the device")
+        if not on_host:
+            # the server reads device frames on its own streams: the work that
+            # produced this one (on the current stream) must be done first
+            torch.cuda.current_stream(x.device).synchronize()
         flags = SUBMIT_HOST if on_host else 0
         if mask.dtype == torch.int32:
             _check_2d(x, "x")

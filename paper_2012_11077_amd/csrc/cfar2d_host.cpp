@@ -66,6 +66,17 @@ constexpr int64_t kMaxDim = int64_t(1) << 30;  // rows, cols
 constexpr int32_t kMaxHalf = 1024;             // any half-width
 constexpr int32_t kMaxTiledHf = 247;           // TILED: 64*8 columns per wave minus two halos
 
+// Most output rows one TILED work unit may take: the byte offsets of the
+// rows a unit reads (its rows and hr + 1 rows above and below) and of its
+// mask rows stay below 2^31.
+static int64_t unit_rows_cap(const cfar_map *m)
+{
+    const int64_t hr = (int64_t)m->win.guard_r + m->win.train_r;
+    const int64_t pitch = m->ld * (m->dtype == CFAR_F32 ? 4 : 8);
+    const int64_t lim = ((int64_t)1 << 31) - 1;
+    return std::min(lim / std::max<int64_t>(pitch, 1) - 2 * hr - 2, lim / std::max<int64_t>(m->ld_mask, 1));
+}
+
 int validate_map(const cfar_map *m, int idx, int form)
 {
     if (!m) return set_error(CFAR_EINVAL, "map %d: NULL descriptor", idx);
@@ -94,6 +105,9 @@ int validate_map(const cfar_map *m, int idx, int form)
     if (form == CFAR_FORM_TILED && w.guard_f + w.train_f > kMaxTiledHf)
         return set_error(CFAR_EINVAL, "map %d: TILED form supports guard_f + train_f <= %d (use PLAIN)", idx,
                          kMaxTiledHf);
+    if (form == CFAR_FORM_TILED && unit_rows_cap(m) < 1)
+        return set_error(CFAR_EINVAL, "map %d: TILED form needs (2 (guard_r + train_r) + 3) rows of the map, and "
+                         "one mask row, to span less than 2^31 bytes", idx);
     if (form == CFAR_FORM_DIRECT) {
         if (direct_lds_bytes(w.guard_r + w.train_r, w.guard_f + w.train_f, m->dtype) > kDirMaxLds)
             return set_error(CFAR_EINVAL, "map %d: DIRECT form supports (%d + 2 hr) x (%d + 2 hf) x element size "
@@ -126,6 +140,7 @@ static int min_units();
 static bool plan_geometry(const cfar_map *m, int k, int rs, Plan *p, int ring_bytes = -1)
 {
     const int hf = m->win.guard_f + m->win.train_f;
+    rs = (int)std::min<int64_t>(rs, unit_rows_cap(m));
     // >= hf + 1 (every prefix read stays inside the strip) and a multiple of
     // max(4, k) (lanes hold either k output columns or none)
     const int a = k > 4 ? k : 4;
@@ -689,6 +704,15 @@ static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, si
     if (g_timing.on) g_timing.recorded = true;
     return CFAR_OK;
 }
+
+// Single map, TILED, its plan chosen as cfar2d does (the allocation-free
+// entry point runs it on its static workspace).
+int tiled_single_ws(const cfar_map *m, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return run_tiled_single(m, choose_plan(m), ws, ws_bytes, stream);
+}
+
+size_t tiled_single_ws_bytes(const cfar_map *m) { return sizeof(BatchHeader) + lut_bytes(m); }
 
 // Single map, DIRECT: table, then every cell sums its own window.  Kernel
 // timing (if on) starts before the first map's stencil and stops after the

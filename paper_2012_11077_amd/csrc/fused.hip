@@ -1,0 +1,601 @@
+// TILED CA-CFAR for gfx950: the persistent fused kernel.
+//
+// Method: Rohman, Andra, Nishimoto, arXiv 2012.11077, Sec. II.B.  The eight
+// corners of eq. (4) (outer window minus guard window) are separable: the
+// row corners are differences of column prefix sums, the column corners
+// differences of row prefixes.  So one pass over the map computes every
+// training sum without writing the integral image of eq. (3):
+//
+//   1. per column of a strip, two FP64 running sums over the rows of the
+//      outer window (r-hr .. r+hr) and of the guard window (r-gr .. r+gr):
+//      each row step adds the row that enters and takes off the row that
+//      leaves, the same FP32 -> FP64 value that was added;
+//   2. an FP64 prefix of those column sums along the strip (in-lane over
+//      the lane's K columns, then a DPP scan over the 64 lanes), published
+//      to LDS;
+//   3. the column corners, prefix differences at +h and -h-1, read back;
+//   4. S_T = outer - guard, T = beta(N_T) * S_T with beta(N) = alpha(N)/N
+//      (eq. 2), decision CUT > T (eq. 1).
+//
+// One wave per work unit: a strip of W = 64*K columns (lane l holds columns
+// cs + l*K .. cs + l*K + K - 1) and a range of output rows of one map.
+// Borders cost nothing in the loads: every row is read through a buffer
+// resource of its own whose size is the map row (F elements), or zero for a
+// row outside the map, so columns right of the map and rows above or below
+// it read as zeros (the clipped sums of eq. 4); lanes left of column 0 read
+// through an offset past any resource.  Only the threshold factor depends on
+// the border: N_T is fixed per column on rows at least hr from the top and
+// bottom, and taken per cell from the table on the rest.
+#include "internal.h"
+
+#include <cmath>
+#include <type_traits>
+
+// Rows of loads in flight in the interior loop: of the lead row (CFAR_PL)
+// and of the other four rows (CFAR_PD); waves per SIMD the FP32 kernel's
+// registers aim at (CFAR_WAVES).  Measured on the uneven batch: the far
+// re-read rows dominate, and depth beats occupancy (4 / 4 at 2 waves).
+#ifndef CFAR_PD
+#define CFAR_PD 4
+#endif
+#ifndef CFAR_PL
+#define CFAR_PL 4
+#endif
+#ifndef CFAR_WAVES
+#define CFAR_WAVES 2
+#endif
+
+namespace cfar {
+
+namespace {
+
+// Word 3 of a raw buffer resource on CDNA (32-bit data format, no swizzle).
+constexpr int kRsrcFlags = 0x00020000;
+// A lane offset past every resource: such accesses read zero and store nothing.
+constexpr uint32_t kOff = 0x80000000u;
+
+#define CFAR_GLOBAL __attribute__((address_space(1)))
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(uint64_t base, uint32_t bytes)
+{
+    const uint32_t lo = uni((uint32_t)base), hi = uni((uint32_t)(base >> 32));
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(uintptr_t)(((uint64_t)hi << 32) | lo), (short)0,
+                                             (int)uni(bytes), kRsrcFlags);
+}
+
+// Rows of one map as buffer resources: row i covers its F elements, a row
+// outside the map covers nothing.
+struct Rows {
+    uint64_t base;   // byte address of row 0
+    uint64_t pitch;  // bytes between rows
+    uint32_t bytes;  // bytes of a row's elements
+    int n;           // rows in the map
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t at(int i) const
+    {
+        const bool in = (uint32_t)i < (uint32_t)n;
+        return rsrc(base + (in ? (uint64_t)(uint32_t)i * pitch : 0ull), in ? bytes : 0u);
+    }
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t at_in(int i) const  // i inside the map
+    {
+        return rsrc(base + (uint64_t)(uint32_t)i * pitch, bytes);
+    }
+};
+
+// K consecutive values of one row at lane byte offset voff (plus the
+// wave-uniform byte offset soff, which the range check leaves out).
+template <int K, typename T>
+__device__ __forceinline__ void ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, T (&v)[K], uint32_t soff = 0u)
+{
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    if constexpr (K * sizeof(T) == 8) {
+        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+        __builtin_memcpy(v, &w, 8);
+    } else {
+#pragma unroll
+        for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q) {
+            const u32x4 w =
+                __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16u * q, soff, 0));
+            __builtin_memcpy((char *)v + 16 * q, &w, 16);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 inclusive prefix sum of one double per lane (DPP on both halves).
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_into(double old, double v)
+{
+    const long long b = __double_as_longlong(v), o = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), CTRL, ROW_MASK,
+                                               0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double v)
+{
+    return dpp_into<CTRL, 0xf>(0.0, v);
+}
+// z15 / z31 carry the broadcast steps' registers from call to call (0.0
+// before the first): the rows those steps leave out stay zero in them.
+__device__ __forceinline__ double wave_scan(double v, double &z15, double &z31)
+{
+    v += dpp_shr<0x111>(v);  // row_shr:1
+    v += dpp_shr<0x112>(v);  // row_shr:2
+    v += dpp_shr<0x114>(v);  // row_shr:4
+    v += dpp_shr<0x118>(v);  // row_shr:8
+    z15 = dpp_into<0x142, 0xa>(z15, v);  // row_bcast:15 into rows 1 and 3
+    v += z15;
+    z31 = dpp_into<0x143, 0xc>(z31, v);  // row_bcast:31 into rows 2 and 3
+    v += z31;
+    return v;
+}
+
+__device__ __forceinline__ int clip_len(int c, int h, int n)
+{
+    const int lo = c - h < 0 ? 0 : c - h;
+    const int hi = c + h > n - 1 ? n - 1 : c + h;
+    return hi - lo + 1;
+}
+
+// LDS layout of one prefix row: position p = l*K + k at [k*64 + l]
+// (consecutive lanes, consecutive words: conflict-free).  Position p + o
+// for element k of lane l, o = q*K + s (0 <= s < K), is element (k+s) mod K
+// of lane l+q, or of lane l+q+1 when k+s >= K; lane indices wrap inside the
+// row (wrapped values only reach lanes without outputs).
+typedef __attribute__((address_space(3))) char lds_char;
+typedef __attribute__((address_space(3))) double lds_double;
+
+template <int K>
+struct Corner {
+    uint32_t addr[K];  // LDS byte addresses in prefix row buffer 0
+    uint32_t own;      // LDS byte address of the lane's own element 0 in buffer 0
+    __device__ __forceinline__ uint32_t addr0() const { return own; }
+    __device__ __forceinline__ void init(int o, int lane, uint32_t base)
+    {
+        own = base + 8u * (uint32_t)lane;
+        asm volatile("" : "+v"(own));
+        const int q = o >= 0 ? o / K : -((-o + K - 1) / K);
+        const int s = o - q * K;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int e = k + s;
+            addr[k] = base + 8u * (uint32_t)((e >= K ? e - K : e) * 64 + ((lane + q + (e >= K ? 1 : 0)) & 63));
+            // an opaque register: the reads then address LDS through it
+            // directly instead of re-adding the LDS base symbol every time
+            asm volatile("" : "+v"(addr[k]));
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One work unit.
+// ---------------------------------------------------------------------------
+template <int K, typename T, bool OUT>
+struct Unit {
+    static constexpr int S = (int)sizeof(T);
+    static constexpr int BUF = 64 * K * 8;  // bytes of one prefix row (outer window, then guard window)
+    // rows of loads in flight: of the lead row (new data), of the other rows
+    static constexpr int PL = K * S >= 32 ? 1 : CFAR_PL;
+    static constexpr int PD = K * S >= 32 ? 1 : CFAR_PD;
+    static constexpr int U = PL > PD ? PL : PD;  // loop unroll
+    static_assert((PL == 1 || PL == 2 || PL == 4) && (PD == 1 || PD == 2 || PD == 4), "slots rotate by powers of 2");
+
+    const MapDesc &d;
+    const int lane;
+    int R, F, hr, gr, hf, gf;
+    int c_lane;
+    int ra, rb;             // output rows of the unit
+    int lo, hi;             // map rows the unit reads: [lo, hi]
+    uint32_t p32, mp32;     // bytes between map rows, between mask rows
+    uint32_t xbytes;        // bytes of a map row's elements
+    uint64_t xlo, mra;      // byte addresses of map row lo and of mask row ra
+    uint32_t voff;          // lane byte offset into a map row (kOff: left of column 0)
+    uint32_t moff;          // lane byte offset of its K mask bytes (kOff: no full ownership)
+    uint32_t poff;          // lane byte offset of a partly owned lane (kOff: none)
+    bool part;              // some lane owns only part of its K columns (wave-uniform)
+    double beta_col[K];     // beta on rows without row clipping
+    Corner<K> c_oh, c_ol, c_ih, c_il;
+    double Co[K], Ci[K];
+    double z15o = 0.0, z31o = 0.0, z15i = 0.0, z31i = 0.0;
+
+    __device__ __forceinline__ Unit(const MapDesc &d_, int strip, int rchunk, int lane_, double *lds_)
+        : d(d_), lane(lane_)
+    {
+        R = d.rows;
+        F = d.cols;
+        hr = d.hr;
+        gr = d.gr;
+        hf = d.hf;
+        gf = d.gf;
+        ra = rchunk * d.rs;
+        rb = min(ra + d.rs, R);
+        lo = max(ra - hr - 1, 0);
+        hi = min(rb - 1 + hr, R - 1);
+        const int c_out0 = strip * d.tw;
+        const int c_out1 = min(c_out0 + d.tw, F);
+        c_lane = c_out0 - d.halo_f + lane * K;
+        // row offsets inside the unit's rows fit 32 bits (checked on the host)
+        p32 = (uint32_t)d.ld * (uint32_t)S;
+        mp32 = (uint32_t)d.ld_mask;
+        xbytes = (uint32_t)F * (uint32_t)S;
+        xlo = (uint64_t)(uintptr_t)d.x + (uint64_t)(uint32_t)lo * (uint64_t)p32;
+        mra = (uint64_t)(uintptr_t)d.mask + (uint64_t)(uint32_t)ra * (uint64_t)mp32;
+        voff = c_lane >= 0 ? (uint32_t)c_lane * (uint32_t)S : kOff;
+        const bool own = c_lane >= c_out0 && c_lane < c_out1;
+        const bool full = own && c_lane + K <= c_out1;
+        moff = full ? (uint32_t)c_lane : kOff;
+        poff = own && !full ? (uint32_t)c_lane : kOff;
+        part = __builtin_amdgcn_ballot_w64(own && !full) != 0ull;
+        const CFAR_GLOBAL double *lut = (const CFAR_GLOBAL double *)d.lut;
+#pragma unroll
+        for (int k = 0; k < K; ++k) beta_col[k] = lut[nt_of(2 * hr + 1, 2 * gr + 1, k)];
+        // corner addresses: the outer window's prefix row, then the guard window's
+        const uint32_t base = (uint32_t)(size_t)(lds_char *)lds_;
+        c_oh.init(hf, lane, base);
+        c_ol.init(-hf - 1, lane, base);
+        c_ih.init(gf, lane, base + BUF);
+        c_il.init(-gf - 1, lane, base + BUF);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            Co[k] = 0.0;
+            Ci[k] = 0.0;
+        }
+    }
+
+    // Training cells of the lane's element k on a row whose clipped outer
+    // and guard windows have nro and nri rows.
+    __device__ __forceinline__ int nt_of(int nro, int nri, int k) const
+    {
+        const int c = min(max(c_lane + k, 0), F - 1);
+        return nro * clip_len(c, hf, F) - nri * clip_len(c, gf, F);
+    }
+
+    // Map row i as a buffer resource of its own: its F elements (columns
+    // right of the map read zero), or nothing for a row outside the map (its
+    // address clamped into the unit's rows).
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t xrow(int i) const
+    {
+        const uint32_t off = uni((uint32_t)(min(max(i, lo), hi) - lo) * p32);
+        return rsrc(xlo + off, (uint32_t)i < (uint32_t)R ? xbytes : 0u);
+    }
+    // Mask row r as a buffer resource of its F bytes.
+    __device__ __forceinline__ __amdgpu_buffer_rsrc_t mrow(int r) const
+    {
+        return rsrc(mra + uni((uint32_t)(r - ra) * mp32), (uint32_t)F);
+    }
+    // 1.0 for a row inside the map, else 0.0
+    __device__ __forceinline__ static double in_map(int i, int n) { return (uint32_t)i < (uint32_t)n ? 1.0 : 0.0; }
+
+    // Column sums before the first output row ra: Co over rows ra-hr-1 ..
+    // ra+hr-1, Ci over rows ra-gr-1 .. ra+gr-1, so that the first step, like
+    // every later one, adds rows r+hr, r+gr and takes off rows r-hr-1, r-gr-1.
+    __device__ __forceinline__ void warm()
+    {
+        constexpr int WB = K * S >= 32 ? 4 : 8;
+        const int w0 = ra - hr - 1, w1 = ra + hr;  // [w0, w1)
+        const int g0 = ra - gr - 1, g1 = ra + gr;
+        for (int i0 = w0; i0 < w1; i0 += WB) {
+            T v[WB][K];
+#pragma unroll
+            for (int j = 0; j < WB; ++j) ld_row<K, T>(xrow(i0 + j), voff, v[j]);
+#pragma unroll
+            for (int j = 0; j < WB; ++j) {
+                const int i = i0 + j;
+                const double wo = i < w1 ? in_map(i, R) : 0.0;
+                const double wi = (i >= g0 && i < g1) ? wo : 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    Co[k] = __builtin_fma(wo, (double)v[j][k], Co[k]);
+                    Ci[k] = __builtin_fma(wi, (double)v[j][k], Ci[k]);
+                }
+            }
+        }
+    }
+
+    // The loads of row step r other than the lead row r+hr: rows r+gr,
+    // r-gr-1, r-hr-1 and the cells under test (row r).
+    struct Rest {
+        T b[K], c[K], e[K], u[K];
+    };
+    __device__ __forceinline__ void load_lead(int r, T (&a)[K]) const { ld_row<K, T>(xrow(r + hr), voff, a); }
+    __device__ __forceinline__ void load_rest(int r, Rest &s) const
+    {
+        ld_row<K, T>(xrow(r + gr), voff, s.b);
+        ld_row<K, T>(xrow(r - gr - 1), voff, s.c);
+        ld_row<K, T>(xrow(r - hr - 1), voff, s.e);
+        ld_row<K, T>(xrow(r), voff, s.u);
+    }
+
+    // Running column sums for row r (rows outside the map weigh zero: they
+    // were never added), then the strip prefix of both into LDS.  (One
+    // buffer per window: a wave's LDS operations complete in order, so the
+    // corner reads of a row are done before the next row's writes.)
+    __device__ __forceinline__ void accumulate_publish(int r, const T (&a)[K], const Rest &s)
+    {
+        const double wa = in_map(r + hr, R), wb = in_map(r + gr, R);
+        const double wc = -in_map(r - gr - 1, R), we = -in_map(r - hr - 1, R);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            Co[k] = __builtin_fma(we, (double)s.e[k], __builtin_fma(wa, (double)a[k], Co[k]));
+            Ci[k] = __builtin_fma(wc, (double)s.c[k], __builtin_fma(wb, (double)s.b[k], Ci[k]));
+        }
+        double po[K], pi[K];
+        po[0] = Co[0];
+        pi[0] = Ci[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+            po[k] = po[k - 1] + Co[k];
+            pi[k] = pi[k - 1] + Ci[k];
+        }
+        // exclusive prefix of the lane totals: the inclusive one minus the lane's own
+        const double eo = wave_scan(po[K - 1], z15o, z31o) - po[K - 1];
+        const double ei = wave_scan(pi[K - 1], z15i, z31i) - pi[K - 1];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            *(lds_double *)(size_t)(c_oh.addr0() + 8 * (k * 64)) = eo + po[k];
+            *(lds_double *)(size_t)(c_ih.addr0() + 8 * (k * 64)) = ei + pi[k];
+        }
+        // LDS operations of one wave complete in order; keep the compiler from
+        // moving the corner reads that follow above these writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // The four column corners of every cell of the lane.
+    struct Corners {
+        double oh[K], ol[K], ih[K], il[K];
+    };
+    __device__ __forceinline__ void corners(Corners &c) const
+    {
+        auto at = [](uint32_t a) { return *(const lds_double *)(size_t)a; };
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            c.oh[k] = at(c_oh.addr[k]);
+            c.ol[k] = at(c_ol.addr[k]);
+            c.ih[k] = at(c_ih.addr[k]);
+            c.il[k] = at(c_il.addr[k]);
+        }
+    }
+
+    // eqs. (1), (2), (4) for the lane's K cells of row r with factors beta,
+    // and the stores.
+    __device__ __forceinline__ void decide(int r, const Corners &c, const T (&u)[K], const double (&beta)[K])
+    {
+        typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+        uint32_t bits[(K + 3) / 4];
+#pragma unroll
+        for (int q = 0; q < (K + 3) / 4; ++q) bits[q] = 0u;
+        double st[K], thr[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            st[k] = (c.oh[k] - c.ol[k]) - (c.ih[k] - c.il[k]);
+            thr[k] = beta[k] * st[k];  // NaN where N_T = 0 (table entry 0): no detection
+            bits[k / 4] |= ((double)u[k] > thr[k]) ? (1u << (8 * (k % 4))) : 0u;
+        }
+        const __amdgpu_buffer_rsrc_t mrs = mrow(r);
+        const uint32_t ms = 0u;
+        if constexpr (K == 2) {
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)bits[0], mrs, moff, ms, 0);
+        } else if constexpr (K == 4) {
+            __builtin_amdgcn_raw_buffer_store_b32(bits[0], mrs, moff, ms, 0);
+        } else {
+            const u32x2 w = {bits[0], bits[1]};
+            __builtin_amdgcn_raw_buffer_store_b64(w, mrs, moff, ms, 0);
+        }
+        if (part) {  // wave-uniform: the lane that straddles the map's last column stores bytes
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bits[k / 4] >> (8 * (k % 4))), mrs,
+                                                     poff == kOff ? kOff : poff + (uint32_t)k, ms, 0);
+        }
+        if constexpr (OUT) {
+            const bool own = moff != kOff || poff != kOff;
+            const uint32_t o8 = own ? (uint32_t)c_lane * 8u : kOff;
+            const int nro = clip_len(r, hr, R), nri = clip_len(r, gr, R);
+            const uint64_t orow = (uint64_t)(uint32_t)r * (uint64_t)d.ld_mask * 8u;
+            if (d.train_sum) {
+                const __amdgpu_buffer_rsrc_t srs = rsrc((uint64_t)(uintptr_t)d.train_sum + orow, (uint32_t)F * 8u);
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, st[k]), srs,
+                                                          o8 == kOff ? kOff : o8 + 8u * k, 0u, 0);
+            }
+            if (d.thresh) {
+                const __amdgpu_buffer_rsrc_t trs = rsrc((uint64_t)(uintptr_t)d.thresh + orow, (uint32_t)F * 8u);
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const double t = nt_of(nro, nri, k) > 0 ? thr[k] : INFINITY;
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, t), trs,
+                                                          o8 == kOff ? kOff : o8 + 8u * k, 0u, 0);
+                }
+            }
+        }
+    }
+    // Rows whose windows the map clips (within hr of the top or bottom):
+    // one after the other, the factors from the table per cell.
+    __device__ __forceinline__ void border_rows(int r0, int r1)
+    {
+        for (int r = r0; r < r1; ++r) {
+            T a[K];
+            Rest s;
+            load_lead(r, a);
+            load_rest(r, s);
+            const int nro = clip_len(r, hr, R), nri = clip_len(r, gr, R);
+            const CFAR_GLOBAL double *lut = (const CFAR_GLOBAL double *)d.lut;
+            double beta[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) beta[k] = lut[nt_of(nro, nri, k)];
+            accumulate_publish(r, a, s);
+            Corners c;
+            corners(c);
+            decide(r, c, s.u, beta);
+        }
+    }
+
+    // One row of the interior loop, slot J: the lead row's loads run PL rows
+    // ahead, the other rows' PD rows; rows past the end are clamped to the
+    // last (loaded again, harmless).
+    template <int J>
+    __device__ __forceinline__ void irow(int r, int r1, T (&lead)[PL][K], Rest (&rest)[PD])
+    {
+        constexpr int JL = J % PL, JR = J % PD;
+        accumulate_publish(r, lead[JL], rest[JR]);
+        T u[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) u[k] = rest[JR].u[k];
+        load_lead(min(r + PL, r1 - 1), lead[JL]);
+        load_rest(min(r + PD, r1 - 1), rest[JR]);
+        Corners c;
+        corners(c);
+        decide(r, c, u, beta_col);
+    }
+
+    // Rows [r0, r1) whose windows lie inside the map: factors fixed per column.
+    __device__ __forceinline__ void interior_rows(int r0, int r1)
+    {
+        if (r0 >= r1) return;
+        T lead[PL][K];
+        Rest rest[PD];
+#pragma unroll
+        for (int j = 0; j < PL; ++j) load_lead(min(r0 + j, r1 - 1), lead[j]);
+#pragma unroll
+        for (int j = 0; j < PD; ++j) load_rest(min(r0 + j, r1 - 1), rest[j]);
+        int r = r0;
+        for (; r + U <= r1; r += U) {
+            irow<0>(r, r1, lead, rest);
+            if constexpr (U > 1) irow<1>(r + 1, r1, lead, rest);
+            if constexpr (U > 2) irow<2>(r + 2, r1, lead, rest);
+            if constexpr (U > 3) irow<3>(r + 3, r1, lead, rest);
+        }
+        const int rem = r1 - r;  // < U
+        if constexpr (U > 1) if (rem > 0) irow<0>(r, r1, lead, rest);
+        if constexpr (U > 2) if (rem > 1) irow<1>(r + 1, r1, lead, rest);
+        if constexpr (U > 3) if (rem > 2) irow<2>(r + 2, r1, lead, rest);
+    }
+
+    __device__ __forceinline__ void run()
+    {
+        warm();
+        const int i0 = min(max(hr, ra), rb);  // first row whose windows the map does not clip
+        const int i1 = max(min(R - hr, rb), i0);
+        border_rows(ra, i0);
+        interior_rows(i0, i1);
+        border_rows(i1, rb);
+    }
+};
+
+// Waves per SIMD the register allocation aims at.
+template <int KS, typename T, bool OUT>
+constexpr int fused_waves()
+{
+    return KS == 8 ? 2 : (sizeof(T) == 4 && !OUT) ? CFAR_WAVES : 2;
+}
+
+// One wave per workgroup; dynamic LDS per wave: the outer and the guard
+// prefix row, 64*KM doubles each.  KS = 24: each unit runs
+// with its map's k (2 or 4); KS = 8: k = 8.
+template <int KS, typename T, bool OUT>
+__global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(fused_waves<KS, T, OUT>())))
+fused_kernel(FusedArgs args)
+{
+    extern __shared__ double fused_lds[];
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        uint32_t u = 0;
+        if (lane == 0) u = __hip_atomic_fetch_add(args.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        u = uni(u);
+        if (u >= args.total_units) break;
+        // descriptor and unit tables are wave-uniform: scalar loads
+        uint32_t local = u;
+        MapDesc d;
+        if (args.descs) {
+            const uint32_t m = uni(((const CFAR_GLOBAL uint32_t *)args.unit_map)[u]);
+            local = u - uni(((const CFAR_GLOBAL uint32_t *)args.unit_base)[m]);
+            const CFAR_GLOBAL uint32_t *src = (const CFAR_GLOBAL uint32_t *)(args.descs + m);
+            uint32_t w[sizeof(MapDesc) / 4];
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(MapDesc) / 4); ++i) w[i] = uni(src[i]);  // keep it in SGPRs
+            __builtin_memcpy(&d, w, sizeof(MapDesc));
+        } else {
+            d = args.single;
+        }
+        const int strip = (int)(local % (uint32_t)d.n_strips);
+        const int rchunk = (int)(local / (uint32_t)d.n_strips);
+        if constexpr (KS == 8) {
+            Unit<8, T, OUT> w(d, strip, rchunk, lane, fused_lds);
+            w.run();
+        } else {
+            if (d.k_cols == 2) {
+                Unit<2, T, OUT> w(d, strip, rchunk, lane, fused_lds);
+                w.run();
+            } else {
+                Unit<4, T, OUT> w(d, strip, rchunk, lane, fused_lds);
+                w.run();
+            }
+        }
+    }
+}
+
+#define CFAR_FUSED_VARIANTS(X_)                                                                        \
+    X_(24, float, false) X_(24, float, true) X_(24, double, false) X_(24, double, true)                 \
+    X_(8, float, false) X_(8, float, true) X_(8, double, false) X_(8, double, true)
+
+const void *fused_fn(int kset, int dtype, bool out)
+{
+#define CFAR_PICK(K_, T_, O_)                                             \
+    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) \
+        return (const void *)fused_kernel<K_, T_, O_>;
+    CFAR_FUSED_VARIANTS(CFAR_PICK)
+#undef CFAR_PICK
+    return nullptr;
+}
+
+}  // namespace
+
+int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes)
+{
+    (void)ring_bytes;
+    constexpr int kDev = 16;
+    static int cached[kDev][8] = {{0}};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+    const int slot = ((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0);
+    int *c = dev < kDev ? &cached[dev][slot] : nullptr;
+    if (c && *c > 0) return *c;
+    const void *fn = fused_fn(kset, dtype, out);
+    int per_cu = 0, cus = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFusedThreads, fused_lds_bytes(kset, 0)) !=
+                   hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    if (cus < 1) cus = 1;
+    if (c) *c = per_cu * cus;
+    return per_cu * cus;
+}
+
+hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, hipStream_t stream)
+{
+    const int resident = fused_resident_blocks(kset, dtype, out, 0);
+    uint32_t blocks = args.total_units;
+    if (blocks > (uint32_t)resident) blocks = (uint32_t)resident;
+    if (blocks == 0) blocks = 1;
+    const size_t lds = fused_lds_bytes(kset, 0);
+#define CFAR_LAUNCH(K_, T_, O_)                                                                                \
+    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) {                                       \
+        hipLaunchKernelGGL((fused_kernel<K_, T_, O_>), dim3(blocks), dim3(kFusedThreads), lds, stream, args); \
+        return hipGetLastError();                                                                              \
+    }
+    CFAR_FUSED_VARIANTS(CFAR_LAUNCH)
+#undef CFAR_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+}  // namespace cfar

@@ -93,6 +93,10 @@ int set_error(int code, const char *fmt, ...);
 int hip_error(hipError_t e, const char *what);
 int validate_map(const cfar_map *m, int idx, int form);
 void drop_batch_ctx(hipStream_t s, void *ws);
+// One map in the TILED form on a caller-given workspace of
+// tiled_single_ws_bytes(m) bytes (m already validated).
+int tiled_single_ws(const cfar_map *m, void *ws, size_t ws_bytes, hipStream_t stream);
+size_t tiled_single_ws_bytes(const cfar_map *m);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (kernels.hip).  All enqueue on `stream` and return the
@@ -155,11 +159,12 @@ inline int ring_bytes_needed(int k, int dtype, int hr, int gr, int budget)
     return 0;
 }
 
-// Dynamic LDS of one wave of the TILED kernel: two prefix rows of 64*kmax
-// doubles, then the ring.
+// Dynamic LDS of one wave of the TILED kernel: the outer and the guard
+// prefix row, 64*kmax doubles each (no row ring: ring_bytes is ignored).
 inline size_t fused_lds_bytes(int kset, int ring_bytes)
 {
-    return (size_t)2 * kmax_of(kset) * 64 * 8 + (size_t)ring_bytes;
+    (void)ring_bytes;
+    return (size_t)2 * kmax_of(kset) * 64 * 8;
 }
 
 }  // namespace cfar

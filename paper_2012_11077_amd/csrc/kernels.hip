@@ -12,20 +12,13 @@
 //       eight corners of eq. (4) read from the FP64 integral image.
 //   lut_kernel
 //       per-map table beta(n) = alpha(n)/n = expm1(-ln(Pfa)/n) for clipped
-//       border windows; also zeroes the work counters of the fused kernels.
-//   fused_kernel
-//       TILED form: persistent, one wave per work unit (a strip of 64*K
-//       columns x rs rows of one map).  The eight corners of eq. (4) are taken
-//       in two separable steps: FP64 running column sums over the outer and
-//       inner window rows hold the four row corners, a wave-wide FP64 row
-//       prefix of those column sums gives the four column corners as
-//       differences read back from LDS.  The integral image itself is never
-//       written; one pass over X.
+//       border windows (NaN at n = 0: no training cells, no detection); also
+//       zeroes the work counters of the fused kernels.
 //   stencil_direct
 //       DIRECT form (the comparison route of Table I): every cell sums its
 //       own training cells from an LDS tile, no integral image.
-// (Detection lists and packed masks are in detections.hip, the map built
-// from a raw record in mapbuild.hip.)
+// (The TILED form's fused kernel is in fused.hip, detection lists and packed
+// masks in detections.hip, the map built from a raw record in mapbuild.hip.)
 #include "internal.h"
 
 #include <cmath>
@@ -293,7 +286,7 @@ __global__ void __launch_bounds__(256) lut_kernel(const MapDesc *__restrict__ de
     const double nl = d->neg_log_pfa;
     const int n_full = d->n_full;
     for (int n = threadIdx.x; n <= n_full; n += blockDim.x)
-        lut[n] = n == 0 ? 0.0 : expm1(nl / (double)n);
+        lut[n] = n == 0 ? __builtin_nan("") : expm1(nl / (double)n);
 }
 
 hipError_t launch_lut(const MapDesc *descs, const MapDesc &single, int n, uint32_t *counter, hipStream_t stream)
@@ -422,762 +415,6 @@ hipError_t launch_stencil_direct(const MapDesc &d, hipStream_t stream)
     else
         hipLaunchKernelGGL(stencil_direct<double>, dim3((unsigned)nb), dim3(256), lds, stream, d);
     return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// TILED form: persistent fused kernel, one instantiation per (K, T).
-//
-// One wave owns a work unit: a strip of W = 64*K map columns (the strip's
-// output columns plus a halo of H >= hf + 1 columns on each side; lane l
-// holds columns l*K .. l*K+K-1 of the strip) and rs output rows.  Per output
-// row r:
-//   1. two FP64 running column sums of the strip, over rows r-hr .. r+hr
-//      (outer window) and r-gr .. r+gr (inner window), each step adding the
-//      row that enters and taking off the row that leaves: the row corners
-//      of eq. (4);
-//   2. an FP64 row prefix of those column sums across the strip (in-lane
-//      serial over K columns, then a DPP scan over the 64 lanes);
-//   3. the column corners of eq. (4): prefix differences at p + h and
-//      p - h - 1, read back from LDS;
-//   4. training sum, N, T = beta(N) * sum, decision, mask store.
-// The next row's loads are issued before the current row is processed.
-// ---------------------------------------------------------------------------
-
-// Global-memory pointers (address space 1): descriptors hand the kernels
-// generic pointers, which would otherwise compile to flat accesses.
-#define CFAR_GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ const CFAR_GLOBAL T *gbl(const T *p) { return (const CFAR_GLOBAL T *)p; }
-template <typename T>
-__device__ __forceinline__ CFAR_GLOBAL T *gbl_w(T *p) { return (CFAR_GLOBAL T *)p; }
-
-// Work-unit modes of the TILED kernel.  FAST: every lane's K columns lie
-// inside the map.  EDGE: a lane's K columns lie all inside or all outside the
-// map (a strip at the left or right border).  GENERAL: anything else.
-enum { kGeneral = 0, kEdge = 1, kFast = 2 };
-
-// Loads of K consecutive values of one row (row: wave-uniform byte pointer)
-// starting at strip column c.  FAST: vector load.  EDGE: vector load, from
-// column 0 (F >= K) for a lane outside the map (`out`), whose values the
-// caller then weighs by zero where they are used (a select here would make
-// the load wait at once).  GENERAL: each column clamped into [0, F) and
-// zeroed outside, so every access stays in bounds.
-template <int K, typename T, int MODE>
-__device__ __forceinline__ void ldk(const CFAR_GLOBAL char *row, int c, int F, bool out, T (&v)[K])
-{
-    if constexpr ((MODE & 3) != kGeneral) {
-        const uint32_t off = (MODE & 3) == kEdge && out ? 0u : (uint32_t)c * (uint32_t)sizeof(T);
-        // K values in one (or two) vector loads, stated as unaligned copies:
-        // rows need not be 16-byte aligned (the memory runs in
-        // unaligned-access mode)
-        if constexpr (K * sizeof(T) == 8) {
-            __builtin_memcpy((char *)v, (const char *)(row + off), 8);
-        } else {
-#pragma unroll
-            for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q)
-                __builtin_memcpy((char *)v + 16 * q, (const char *)(row + off + 16u * q), 16);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int cc = c + k;
-            const int cl = min(max(cc, 0), F - 1);
-            const T t = *(const CFAR_GLOBAL T *)(row + (uint32_t)cl * (uint32_t)sizeof(T));
-            v[k] = (cc >= 0 && cc < F) ? t : T(0);
-        }
-    }
-}
-
-// acc += s * v with s = 1.0 (row entering the window), -1.0 (row leaving
-// it) or 0.0 (row outside the map): branch-free, and bit-identical to
-// adding, subtracting or skipping the row.
-template <int K, typename T>
-__device__ __forceinline__ void acc_row(double (&a)[K], const T (&v)[K], double s)
-{
-#pragma unroll
-    for (int k = 0; k < K; ++k) a[k] = __builtin_fma(s, (double)v[k], a[k]);
-}
-
-// Lane-major LDS layout of one prefix row: position p = l*K + k at
-// [k*64 + l].  Position p + o for element k of lane l, with o = q*K + s
-// (0 <= s < K), is element (k+s) mod K of lane l+q, or of lane l+q+1 when
-// k+s >= K.  The K addresses depend only on o and the lane, so they are
-// formed once per work unit.  Lane indices wrap inside the row so every
-// address stays in the wave's region (wrapped values only reach positions
-// that are not outputs).
-template <int K>
-struct OffsetRead {
-    int addr[K];
-    __device__ __forceinline__ void init(int o, int lane)
-    {
-        const int q = o >= 0 ? o / K : -((-o + K - 1) / K);
-        const int s = o - q * K;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int e = k + s;
-            addr[k] = (e >= K ? e - K : e) * 64 + ((lane + q + (e >= K ? 1 : 0)) & 63);
-        }
-    }
-    __device__ __forceinline__ double get(const double *__restrict__ q, int k) const { return q[addr[k]]; }
-};
-
-// Rows whose loads are in flight in the interior loop.
-#ifndef CFAR_PREFETCH_ROWS
-#define CFAR_PREFETCH_ROWS 2
-#endif
-template <int K, typename T>
-constexpr int prefetch_rows() { return K * sizeof(T) >= 32 ? 2 : CFAR_PREFETCH_ROWS; }
-#ifndef CFAR_PREFETCH_ROWS_FULL
-#define CFAR_PREFETCH_ROWS_FULL 3
-#endif
-template <int K, typename T>
-constexpr int prefetch_rows_full() { return K * sizeof(T) >= 32 ? 3 : CFAR_PREFETCH_ROWS_FULL; }
-// Rows loaded together in the warm-up.
-template <int K, typename T>
-constexpr int warm_rows() { return K * sizeof(T) >= 32 ? 4 : 8; }
-// Word 3 of a raw buffer resource on CDNA (32-bit data format, no swizzle).
-constexpr int kBufferFlags = 0x00020000;
-
-// K consecutive values of one row through a buffer resource: lane byte
-// offset voff, wave-uniform row byte offset soff (any alignment of the
-// element type: the memory runs in unaligned-access mode).
-template <int K, typename T>
-__device__ __forceinline__ void ldk_buf(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, T (&v)[K])
-{
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    if constexpr (K * sizeof(T) == 8) {
-        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
-        __builtin_memcpy(v, &w, 8);
-    } else {
-#pragma unroll
-        for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q) {
-            const u32x4 w = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16u * q, soff, 0));
-            __builtin_memcpy((char *)v + 16 * q, &w, 16);
-        }
-    }
-}
-// FAST units: the strip's output columns are at least hf away from both map
-// borders (only rows can be clipped: N = n_full on interior rows).  EDGE
-// units: a lane's K columns are all inside or all outside the map; interior
-// rows clip only columns, so N and beta are fixed per lane.  In both, lanes
-// hold either K output columns or none.
-//
-// Window sums run as two FP64 accumulators per column, the outer (rows
-// r-hr .. r+hr) and the inner (rows r-gr .. r+gr) column sum: each step adds
-// the row entering the window and takes off the row leaving it, the same
-// value that was added, so a row outside the map (never added) is neither.
-//
-// Interior rows of FAST and EDGE units without the optional outputs run a
-// straight-line loop (no branches, no clipping) fed through a buffer
-// resource with several rows in flight; border rows, general units and maps
-// with the optional outputs run a plain loop.
-template <int K, typename T, int MODE, bool OUT>
-__device__ void fused_unit(const MapDesc &d, int strip, int rchunk, int cs, double *__restrict__ qo,
-                           double *__restrict__ qi, T *__restrict__ ring, int ring_bytes, int lane)
-{
-    const int R = d.rows, F = d.cols;
-    const int hr = d.hr, hf = d.hf, gr = d.gr, gf = d.gf;
-    const int c_out0 = strip * d.tw;
-    const int c_out1 = min(c_out0 + d.tw, F);
-    // cs: map column of strip position 0, c_out0 - H, or for a right-aligned
-    // last strip F + H - 64K (then c_out0 - cs >= H still holds)
-    const int ra = rchunk * d.rs;
-    const int rb = min(ra + d.rs, R);
-    const int c_lane = cs + lane * K;
-    const T *__restrict__ X = (const T *)d.x;
-    const int64_t ld = d.ld;
-
-    const bool lane_any_out = (c_lane + K > c_out0) && (c_lane < c_out1);
-    // first own column of the lane (0 but in a right-aligned strip, whose
-    // first output column may fall inside a lane: that lane stores bytes)
-    const int k_own0 = max(c_out0 - c_lane, 0);
-    const bool lane_col_interior = (c_lane >= hf) && (c_lane + K - 1 + hf < F);
-    // EDGE: a lane outside the map loads column 0 and weighs it by zero
-    constexpr int BM = MODE & 3;  // FAST, EDGE or GENERAL
-    const bool lane_outside = BM == kEdge && (c_lane < 0 || c_lane >= F);
-    const double lane_w = lane_outside ? 0.0 : 1.0;
-    const double beta_full = gbl(d.lut)[d.n_full];
-    // EDGE: beta per lane on rows without row clipping (NaN where N = 0: no
-    // detection)
-    double beta_lane[BM == kEdge ? K : 1];
-    if constexpr (BM == kEdge) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int jc = min(max(c_lane + k, 0), F - 1);
-            const int nt = (2 * hr + 1) * clip_len(jc, hf, F) - (2 * gr + 1) * clip_len(jc, gf, F);
-            beta_lane[k] = nt > 0 ? gbl(d.lut)[nt] : __builtin_nan("");
-        }
-    }
-
-    OffsetRead<K> rd_oh, rd_ol, rd_ih, rd_il;
-    rd_oh.init(hf, lane);
-    rd_ol.init(-hf - 1, lane);
-    rd_ih.init(gf, lane);
-    rd_il.init(-gf - 1, lane);
-
-    auto rowp = [&](int i) -> const CFAR_GLOBAL char * {
-        const int ic = min(max(i, 0), R - 1);
-        return (const CFAR_GLOBAL char *)gbl(X + (int64_t)ic * ld);
-    };
-
-    double Co[K], Ci[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) { Co[k] = 0.0; Ci[k] = 0.0; }
-
-    // Warm-up: Co over rows [ra-hr-1, ra+hr-1], Ci over rows [ra-gr-1,
-    // ra+gr-1] (rows inside the map), so the first step, like every later
-    // one, adds rows r+hr, r+gr and takes off rows r-hr-1, r-gr-1.
-    {
-        const int w0 = ra - hr - 1, w1 = ra + hr, g0 = ra - gr - 1, g1 = ra + gr;
-        for (int i0 = w0; i0 < w1; i0 += warm_rows<K, T>()) {
-            T w[warm_rows<K, T>()][K];
-#pragma unroll
-            for (int j = 0; j < warm_rows<K, T>(); ++j) ldk<K, T, MODE>(rowp(i0 + j), c_lane, F, lane_outside, w[j]);
-#pragma unroll
-            for (int j = 0; j < warm_rows<K, T>(); ++j) {
-                const int i = i0 + j;
-                const bool in = i >= 0 && i < R && i < w1;
-                acc_row<K, T>(Co, w[j], in ? lane_w : 0.0);
-                acc_row<K, T>(Ci, w[j], (in && i >= g0 && i < g1) ? lane_w : 0.0);
-            }
-        }
-    }
-
-    // Row prefix of the two column sums across the strip (in-lane serial,
-    // then a DPP scan over the lanes), published in LDS: the row corners of
-    // eq. (4) are in the column sums, the column corners are read back at
-    // offsets +-h.
-    double z15o = 0.0, z31o = 0.0, z15i = 0.0, z31i = 0.0;  // see wave_incl_scan_carried
-    auto publish = [&]() {
-        double po[K], pi[K];
-        po[0] = Co[0];
-        pi[0] = Ci[0];
-#pragma unroll
-        for (int k = 1; k < K; ++k) {
-            po[k] = po[k - 1] + Co[k];
-            pi[k] = pi[k - 1] + Ci[k];
-        }
-        // exclusive prefix of the lane totals: the inclusive one minus the lane's own
-        const double eo = wave_incl_scan_carried(po[K - 1], z15o, z31o) - po[K - 1];
-        const double ei = wave_incl_scan_carried(pi[K - 1], z15i, z31i) - pi[K - 1];
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            qo[k * 64 + lane] = eo + po[k];
-            qi[k * 64 + lane] = ei + pi[k];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    };
-    // Any row: b = rows r+hr, r+gr, r-gr-1, r-hr-1, r; rows outside the map
-    // are neither added nor taken off.
-    auto accumulate = [&](int r, const T(&b)[5][K]) {
-        const double so = r + hr < R ? lane_w : 0.0, si = r + gr < R ? lane_w : 0.0;
-        const double to = r - hr - 1 >= 0 ? -lane_w : 0.0, ti = r - gr - 1 >= 0 ? -lane_w : 0.0;
-        acc_row<K, T>(Co, b[0], so);
-        acc_row<K, T>(Co, b[3], to);
-        acc_row<K, T>(Ci, b[1], si);
-        acc_row<K, T>(Ci, b[2], ti);
-        publish();
-    };
-    auto train_sum_at = [&](int k) -> double {
-        // column corners of eq. (4): box = Q(p + h) - Q(p - h - 1), outer minus inner
-        return (rd_oh.get(qo, k) - rd_ol.get(qo, k)) - (rd_ih.get(qi, k) - rd_il.get(qi, k));
-    };
-    // packed stores need 4-byte aligned mask rows and a strip start on a
-    // multiple of min(K, 4) columns; else bytes
-    const bool mvec = (d.vec_ok & 2) != 0 && (cs % (K < 4 ? K : 4)) == 0;
-    auto store_bits = [&](CFAR_GLOBAL uint8_t *dst, const uint32_t(&bits)[(K + 3) / 4]) {
-        if (!mvec || (BM == kEdge && k_own0 > 0)) {
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k >= k_own0) dst[k] = (uint8_t)(bits[k / 4] >> (8 * (k % 4)));
-            return;
-        }
-        if constexpr (K == 2) {
-            __builtin_nontemporal_store((uint16_t)bits[0], (CFAR_GLOBAL uint16_t *)dst);
-        } else {
-#pragma unroll
-            for (int q = 0; q < K / 4; ++q) __builtin_nontemporal_store(bits[q], (CFAR_GLOBAL uint32_t *)dst + q);
-        }
-    };
-    // Interior row of a FAST unit (N = n_full, beta = beta_full) or an EDGE
-    // unit (beta per lane); every lane computes, lanes with outputs store.
-    auto decide_fast = [&](const T(&xcut)[K], uint32_t(&bits)[(K + 3) / 4]) {
-#pragma unroll
-        for (int q = 0; q < (K + 3) / 4; ++q) bits[q] = 0u;
-        // every corner read is issued before the first is used: the LDS
-        // round trips overlap instead of following one another
-        double oh[K], ol[K], ih[K], il[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            oh[k] = rd_oh.get(qo, k);
-            ol[k] = rd_ol.get(qo, k);
-            ih[k] = rd_ih.get(qi, k);
-            il[k] = rd_il.get(qi, k);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double beta = BM == kEdge ? beta_lane[BM == kEdge ? k : 0] : beta_full;
-            const double thr = beta * ((oh[k] - ol[k]) - (ih[k] - il[k]));
-            bits[k / 4] |= ((double)xcut[k] > thr) ? (1u << (8 * (k % 4))) : 0u;
-        }
-    };
-    auto output_fast = [&](int r, const T(&xcut)[K]) {
-        uint32_t bits[(K + 3) / 4];
-        decide_fast(xcut, bits);
-        CFAR_GLOBAL uint8_t *mdst = gbl_w(d.mask) + (int64_t)r * d.ld_mask + c_lane;
-        if (lane_any_out) store_bits(mdst, bits);
-    };
-    // Any row: N and beta per cell; every cell is computed, owned cells
-    // store their byte.  The per-cell table loads are issued by prep() before
-    // the next row's loads, so waiting for them never waits for the prefetch.
-    struct Prep {
-        int nt[K];
-        double beta[K];
-    };
-    auto prep = [&](int r, Prep &pp) {
-        const int nro = clip_len(r, hr, R), nri = clip_len(r, gr, R);
-        const bool interior = (r >= hr) && (r + hr < R) && lane_col_interior;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int jc = min(max(c_lane + k, 0), F - 1);
-            pp.nt[k] = interior ? d.n_full : nro * clip_len(jc, hf, F) - nri * clip_len(jc, gf, F);
-            pp.beta[k] = gbl(d.lut)[pp.nt[k]];
-        }
-    };
-    auto output_general = [&](int r, const T(&xcut)[K], const Prep &pp) {
-        const int64_t orow = (int64_t)r * d.ld_mask;
-        CFAR_GLOBAL uint8_t *mrow = gbl_w(d.mask) + orow;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double st = train_sum_at(k);
-            const int j = c_lane + k;
-            const double thr = pp.beta[k] * st;
-            const bool own = j >= c_out0 && j < c_out1;
-            if (own) mrow[j] = (uint8_t)(pp.nt[k] > 0 && (double)xcut[k] > thr);
-            if constexpr (OUT) {
-                if (own) {
-                    if (d.train_sum) gbl_w(d.train_sum)[orow + j] = st;
-                    if (d.thresh) gbl_w(d.thresh)[orow + j] = pp.nt[k] > 0 ? thr : INFINITY;
-                }
-            }
-        }
-    };
-    auto issue = [&](int r, T(&b)[5][K]) {
-        ldk<K, T, MODE>(rowp(r + hr), c_lane, F, lane_outside, b[0]);
-        ldk<K, T, MODE>(rowp(r + gr), c_lane, F, lane_outside, b[1]);
-        ldk<K, T, MODE>(rowp(r - gr - 1), c_lane, F, lane_outside, b[2]);
-        ldk<K, T, MODE>(rowp(r - hr - 1), c_lane, F, lane_outside, b[3]);
-        ldk<K, T, MODE>(rowp(r), c_lane, F, lane_outside, b[4]);
-    };
-    auto general_rows = [&](int r0, int r1) {
-        for (int r = r0; r < r1; ++r) {
-            T b[5][K];
-            Prep pp;
-            prep(r, pp);
-            issue(r, b);
-            accumulate(r, b);
-            output_general(r, b[4], pp);
-            __builtin_amdgcn_wave_barrier();
-        }
-    };
-
-    // Interior rows of FAST and EDGE units without the optional outputs
-    // (EDGE: lanes outside the map load column 0, weighed by zero): every
-    // row of both windows inside the map, so the accumulators take plain adds and
-    // subtractions.  Rows come through a buffer resource over the rows this
-    // loop touches, with wave-uniform row offsets that advance one row per
-    // step and PD rows in flight, and through a per-wave LDS ring (slot of
-    // row i = i mod D, kept as running indices):
-    //   FULL: one global load per row (lead row r+hr, also written into a
-    //         ring of D = 2hr+2 rows, whence rows r+gr, r-gr-1, r-hr-1 and
-    //         the cells under test come back);
-    //   else: three global loads per row (rows r+hr, r+gr, r-hr-1); row
-    //         r+gr also goes into a ring of D = 2gr+2 rows, whence row
-    //         r-gr-1 and the cells under test come back.
-    // Needs r0 > hr, r1 <= R - hr and the rows' byte span below 2^31.
-    auto interior = [&](auto full_tag, int r0, int r1) {
-        constexpr bool FULL = decltype(full_tag)::value;
-        if (r0 >= r1) return;
-        constexpr int PD = FULL ? prefetch_rows_full<K, T>() : prefetch_rows<K, T>();
-        constexpr int NL = FULL ? 1 : 3;  // global loads per row
-        const int D = FULL ? 2 * hr + 2 : 2 * gr + 2;
-        const int hw = FULL ? hr : gr;  // half-width of the rows the ring serves
-        const uint32_t ldb = (uint32_t)ld * (uint32_t)sizeof(T);
-        const int row_lo = r0 - hr - 1;
-        const int row_hi = r1 - 1 + hr;
-        // base and extent are wave-uniform: say so, or the compiler wraps
-        // every buffer access in a loop over distinct descriptors
-        const uint64_t base = (uint64_t)(uintptr_t)(X + (int64_t)row_lo * ld);
-        const uint32_t base_lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
-        const uint32_t base_hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
-        const int extent = (int)__builtin_amdgcn_readfirstlane((uint32_t)(row_hi - row_lo) * ldb +
-                                                               (uint32_t)F * (uint32_t)sizeof(T));
-        const __amdgpu_buffer_rsrc_t rsx = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(uintptr_t)(((uint64_t)base_hi << 32) | base_lo), (short)0, extent, kBufferFlags);
-        const uint32_t voff = lane_outside ? 0u : (uint32_t)c_lane * (uint32_t)sizeof(T);  // EDGE: column 0
-        uint32_t so_lead = (uint32_t)(r0 + hr - row_lo) * ldb;
-        uint32_t so_glead = (uint32_t)(r0 + gr - row_lo) * ldb;
-        uint32_t so_lag = 0;
-        auto load = [&](T(&b)[NL][K]) {
-            ldk_buf<K, T>(rsx, voff, so_lead, b[0]);
-            so_lead += ldb;
-            if constexpr (!FULL) {
-                ldk_buf<K, T>(rsx, voff, so_glead, b[1]);
-                ldk_buf<K, T>(rsx, voff, so_lag, b[2]);
-                so_glead += ldb;
-                so_lag += ldb;
-            }
-        };
-        // a lane's K values of one ring row, moved as 16-byte LDS accesses
-        // where K * sizeof(T) is a multiple of 16 (aligned: the ring starts on
-        // a 4 KiB boundary), conflict-free at that lane stride
-        typedef uint32_t r32x4 __attribute__((ext_vector_type(4)));
-        auto ring_put = [&](int slot, const T(&v)[K]) {
-            char *p = (char *)(ring + (slot * 64 + lane) * K);
-            if constexpr (K * sizeof(T) % 16 == 0) {
-#pragma unroll
-                for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q) {
-                    r32x4 w;
-                    __builtin_memcpy(&w, (const char *)v + 16 * q, 16);
-                    *(r32x4 *)(p + 16 * q) = w;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < K; ++k) ((T *)p)[k] = v[k];
-            }
-        };
-        auto ring_get = [&](int slot, T(&v)[K]) {
-            const char *p = (const char *)(ring + (slot * 64 + lane) * K);
-            if constexpr (K * sizeof(T) % 16 == 0) {
-#pragma unroll
-                for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q) {
-                    const r32x4 w = *(const r32x4 *)(p + 16 * q);
-                    __builtin_memcpy((char *)v + 16 * q, &w, 16);
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < K; ++k) v[k] = ((const T *)p)[k];
-            }
-        };
-        {
-            int sl = (r0 - hw - 1) % D;
-            uint32_t so = (uint32_t)(hr - hw) * ldb;  // row r0-hw-1
-            for (int i = 0; i < D - 1; ++i) {         // rows r0-hw-1 .. r0+hw-1
-                T v[K];
-                ldk_buf<K, T>(rsx, voff, so, v);
-                ring_put(sl, v);
-                so += ldb;
-                sl = sl + 1 == D ? 0 : sl + 1;
-            }
-        }
-        // running slots: rows r+hw (written), r, and for FULL r+gr, r-gr-1
-        int s_w = (r0 + hw) % D, s_c = r0 % D, s_g = (r0 + gr) % D, s_gl = (r0 - gr - 1 + D) % D;
-        // The mask rows r0..r1-1 through a buffer resource too; a lane
-        // without output columns stores past its end, where the store is
-        // dropped, so the store needs no branch (and no alignment: the
-        // packed store of a lane may straddle dwords)
-        const uint64_t mbase = (uint64_t)(uintptr_t)(d.mask + (int64_t)r0 * d.ld_mask);
-        const uint32_t mb_lo = __builtin_amdgcn_readfirstlane((uint32_t)mbase);
-        const uint32_t mb_hi = __builtin_amdgcn_readfirstlane((uint32_t)(mbase >> 32));
-        const int mext = (int)__builtin_amdgcn_readfirstlane((uint32_t)(r1 - 1 - r0) * (uint32_t)d.ld_mask +
-                                                             (uint32_t)F);
-        const __amdgpu_buffer_rsrc_t rsm = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(uintptr_t)(((uint64_t)mb_hi << 32) | mb_lo), (short)0, mext, kBufferFlags);
-        // (EDGE: a lane of a right-aligned last strip may own only its last
-        // K - k_own0 columns; it stores those as bytes, the packed store
-        // skips it)
-        const uint32_t moff = lane_any_out && k_own0 == 0 ? (uint32_t)c_lane : 0x80000000u;
-        const bool unit_partial = BM == kEdge && __ballot(lane_any_out && k_own0 > 0) != 0ull;
-        const uint32_t mstep_u = __builtin_amdgcn_readfirstlane((uint32_t)d.ld_mask);
-        uint32_t so_m = 0;
-        auto next = [&](int v) { return v + 1 == D ? 0 : v + 1; };
-        auto step = [&](const T(&b)[NL][K]) {
-            T gle[K], gla[K], la[K], xc[K];
-            const int s_l = next(s_w);  // row r-hw-1 = r+hw+1 mod D
-            {
-                ring_put(s_w, b[FULL ? 0 : NL - 2]);
-                if constexpr (FULL)
-                    ring_get(s_l, la);
-                else
-                    ring_get(s_l, gla);
-                ring_get(s_c, xc);
-                if constexpr (FULL) {
-                    ring_get(s_g, gle);
-                    ring_get(s_gl, gla);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < K; ++k) {
-                        gle[k] = b[NL - 2][k];
-                        la[k] = b[NL - 1][k];
-                    }
-                }
-            }
-            s_w = s_l;
-            s_c = next(s_c);
-            if constexpr (FULL) {
-                s_g = next(s_g);
-                s_gl = next(s_gl);
-            }
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if constexpr (BM == kEdge) {  // lanes outside the map weigh zero
-                    Co[k] = __builtin_fma(-lane_w, (double)la[k], __builtin_fma(lane_w, (double)b[0][k], Co[k]));
-                    Ci[k] = __builtin_fma(-lane_w, (double)gla[k], __builtin_fma(lane_w, (double)gle[k], Ci[k]));
-                } else {
-                    Co[k] = (Co[k] + (double)b[0][k]) - (double)la[k];
-                    Ci[k] = (Ci[k] + (double)gle[k]) - (double)gla[k];
-                }
-            }
-            publish();
-            uint32_t bits[(K + 3) / 4];
-            decide_fast(xc, bits);
-            if constexpr (K == 2) {
-                __builtin_amdgcn_raw_buffer_store_b16((uint16_t)bits[0], rsm, moff, so_m, 0);
-            } else if constexpr (K == 4) {
-                __builtin_amdgcn_raw_buffer_store_b32(bits[0], rsm, moff, so_m, 0);
-            } else {
-                typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-                const u32x2 w = {bits[0], bits[1]};
-                __builtin_amdgcn_raw_buffer_store_b64(w, rsm, moff, so_m, 0);
-            }
-            if (unit_partial) {  // wave-uniform
-                const uint32_t pboff = lane_any_out && k_own0 > 0 ? (uint32_t)c_lane : 0x80000000u;
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bits[k / 4] >> (8 * (k % 4))), rsm,
-                                                         k >= k_own0 ? pboff + (uint32_t)k : 0x80000000u, so_m, 0);
-            }
-            so_m += mstep_u;
-        };
-        T buf[PD][NL][K];
-        int r = r0;
-        if (r1 - r0 >= PD) {
-#pragma unroll
-            for (int j = 0; j < PD; ++j) load(buf[j]);
-            for (; r + 2 * PD <= r1; r += PD) {
-#pragma unroll
-                for (int j = 0; j < PD; ++j) {
-                    step(buf[j]);
-                    load(buf[j]);
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < PD; ++j) step(buf[j]);
-            r += PD;
-        }
-        for (; r < r1; ++r) {
-            T b[NL][K];
-            load(b);
-            step(b);
-        }
-    };
-    // Interior rows without the ring (wide guard windows): five loads per row.
-    auto pipelined_fast5 = [&](int r0, int r1) {
-        if (r0 >= r1) return;
-        T A[5][K], B[5][K];
-        issue(r0, A);
-        int r = r0;
-        for (; r + 1 < r1; r += 2) {
-            issue(r + 1, B);  // rows are clamped, so issuing past the end is harmless
-            accumulate(r, A);
-            output_fast(r, A[4]);
-            issue(r + 2, A);
-            accumulate(r + 1, B);
-            output_fast(r + 1, B[4]);
-        }
-        if (r < r1) {
-            accumulate(r, A);
-            output_fast(r, A[4]);
-        }
-    };
-    auto pipelined_general = [&](int r0, int r1) {
-        if (r0 >= r1) return;
-        T A[5][K], B[5][K];
-        Prep PA, PB;
-        issue(r0, A);
-        int r = r0;
-        for (; r + 1 < r1; r += 2) {
-            prep(r, PA);
-            issue(r + 1, B);
-            accumulate(r, A);
-            output_general(r, A[4], PA);
-            prep(r + 1, PB);
-            issue(r + 2, A);
-            accumulate(r + 1, B);
-            output_general(r + 1, B[4], PB);
-        }
-        if (r < r1) {
-            prep(r, PA);
-            accumulate(r, A);
-            output_general(r, A[4], PA);
-        }
-    };
-    if (BM != kGeneral && !OUT) {
-        const bool span_ok = (d.vec_ok & 4) != 0;
-        const int ring_rows = ring_bytes / (64 * K * (int)sizeof(T));
-        const int r_in0 = min(max(hr + 1, ra), rb);
-        const int r_in1 = max(min(R - hr, rb), r_in0);
-        general_rows(ra, r_in0);
-        if (BM == kFast && span_ok && 2 * hr + 2 <= ring_rows)  // (EDGE: guard ring only, for registers)
-            interior(std::true_type(), r_in0, r_in1);
-        else if (span_ok && 2 * gr + 2 <= ring_rows)
-            interior(std::false_type(), r_in0, r_in1);
-        else
-            pipelined_fast5(r_in0, r_in1);
-        general_rows(r_in1, rb);
-    } else {
-        pipelined_general(ra, rb);
-    }
-}
-
-__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// One wave per workgroup; dynamic LDS per wave: the two prefix rows
-// (2*K*64 doubles), then the ring of args.ring_rows rows of 64*K values.
-// Mode of one work unit (see fused_unit) and its run.
-template <int K, typename T, bool OUT>
-__device__ __forceinline__ void run_unit(const MapDesc &d, int strip, int rchunk, double *qo, double *qi, void *ring,
-                                         int ring_bytes, int lane)
-{
-    const int F = d.cols, W = 64 * K;
-    int cs = strip * d.tw - d.halo_f;
-    const bool halo_ok = (d.halo_f % K) == 0;
-    // The last strip, if its lanes would straddle column F (F not a multiple
-    // of K), is right-aligned instead: its last lanes then end on column
-    // F + H - 1, so column F falls on a lane boundary, and since its outputs
-    // start within the last tw columns it still reaches back H columns
-    // before them.  (Earlier strips that reach past F take the general path.)
-    if (halo_ok && strip == d.n_strips - 1 && cs + W > F && F % K != 0 && F + d.halo_f - W >= 0)
-        cs = F + d.halo_f - W;
-    const bool inside = cs >= 0 && cs + W <= F;
-    // EDGE needs lanes wholly inside or outside: columns 0 and F, where they
-    // fall inside the strip, on lane boundaries
-    const bool left_ok = cs >= 0 || (cs % K) == 0;
-    const bool edge_ok = F >= K && ((F - cs) % K == 0 || cs + W <= F) && left_ok;
-    T *rg = (T *)ring;
-    if (halo_ok && inside) {
-        fused_unit<K, T, kFast, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
-    } else if (halo_ok && edge_ok) {
-        fused_unit<K, T, kEdge, OUT>(d, strip, rchunk, cs, qo, qi, rg, ring_bytes, lane);
-    } else {
-        fused_unit<K, T, kGeneral, OUT>(d, strip, rchunk, strip * d.tw - d.halo_f, qo, qi, rg, ring_bytes, lane);
-    }
-}
-
-#ifndef CFAR_WAVES_16B
-#define CFAR_WAVES_16B 3
-#endif
-// Waves per SIMD the register allocation aims at, by bytes per lane and row
-// (the LDS of one wave is small, so registers set the occupancy).
-template <int KS, typename T, bool OUT>
-constexpr int fused_waves()
-{
-    return KS == 8 ? 1 : sizeof(T) == 4 ? (OUT ? 2 : CFAR_WAVES_16B) : (OUT ? 1 : 2);
-}
-
-// One wave per workgroup; dynamic LDS per wave: the two prefix rows
-// (2*kmax*64 doubles), then the ring of args.ring_bytes.  KS = 24: each
-// unit runs with its map's k (2 or 4); KS = 8: k = 8.
-template <int KS, typename T, bool OUT>
-__global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(fused_waves<KS, T, OUT>())))
-fused_kernel(FusedArgs args)
-{
-    constexpr int KM = KS == 8 ? 8 : 4;
-    extern __shared__ double fused_lds[];
-    const int lane = threadIdx.x & 63;
-    double *qo = fused_lds;
-    double *qi = fused_lds + KM * 64;
-    T *ring = (T *)(fused_lds + 2 * KM * 64);
-    for (;;) {
-        uint32_t u = 0;
-        if (lane == 0) u = __hip_atomic_fetch_add(args.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        u = wave_uniform(u);
-        if (u >= args.total_units) break;
-        // descriptor and unit tables are wave-uniform: global (scalar) loads
-        uint32_t local = u;
-        MapDesc d;
-        if (args.descs) {
-            const uint32_t m = wave_uniform(gbl(args.unit_map)[u]);
-            local = u - wave_uniform(gbl(args.unit_base)[m]);
-            const CFAR_GLOBAL uint32_t *src = (const CFAR_GLOBAL uint32_t *)gbl(args.descs + m);
-            uint32_t w[sizeof(MapDesc) / 4];
-#pragma unroll
-            for (int i = 0; i < (int)(sizeof(MapDesc) / 4); ++i) w[i] = src[i];
-            __builtin_memcpy(&d, w, sizeof(MapDesc));
-        } else {
-            d = args.single;
-        }
-        const int strip = (int)(local % (uint32_t)d.n_strips);
-        const int rchunk = (int)(local / (uint32_t)d.n_strips);
-        if constexpr (KS == 8) {
-            run_unit<8, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
-        } else {
-            if (d.k_cols == 2)
-                run_unit<2, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
-            else
-                run_unit<4, T, OUT>(d, strip, rchunk, qo, qi, ring, args.ring_bytes, lane);
-        }
-    }
-}
-
-#define CFAR_FUSED_VARIANTS(X_)                                                                        \
-    X_(24, float, false) X_(24, float, true) X_(24, double, false) X_(24, double, true)                 \
-    X_(8, float, false) X_(8, float, true) X_(8, double, false) X_(8, double, true)
-
-static const void *fused_fn(int kset, int dtype, bool out)
-{
-#define CFAR_PICK(K_, T_, O_)                                             \
-    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) \
-        return (const void *)fused_kernel<K_, T_, O_>;
-    CFAR_FUSED_VARIANTS(CFAR_PICK)
-#undef CFAR_PICK
-    return nullptr;
-}
-
-int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes)
-{
-    // cache: device x kernel x ring size (in 512-byte steps)
-    constexpr int kSteps = 129;
-    static int cached[16][8][kSteps] = {{{0}}};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
-    const int slot = ((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0);
-    const int step = ring_bytes % 512 == 0 && ring_bytes / 512 < kSteps ? ring_bytes / 512 : -1;
-    int *c = dev < 16 && step >= 0 ? &cached[dev][slot][step] : nullptr;
-    if (c && *c > 0) return *c;
-    const void *fn = fused_fn(kset, dtype, out);
-    int per_cu = 0, cus = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFusedThreads,
-                                                            fused_lds_bytes(kset, ring_bytes)) != hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
-    if (cus < 1) cus = 1;
-    if (c) *c = per_cu * cus;
-    return per_cu * cus;
-}
-
-hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, hipStream_t stream)
-{
-    const int resident = fused_resident_blocks(kset, dtype, out, args.ring_bytes);
-    uint32_t blocks = args.total_units;
-    if (blocks > (uint32_t)resident) blocks = (uint32_t)resident;
-    if (blocks == 0) blocks = 1;
-    const size_t lds = fused_lds_bytes(kset, args.ring_bytes);
-#define CFAR_LAUNCH(K_, T_, O_)                                                                                \
-    if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) {                                       \
-        hipLaunchKernelGGL((fused_kernel<K_, T_, O_>), dim3(blocks), dim3(kFusedThreads), lds, stream, args); \
-        return hipGetLastError();                                                                              \
-    }
-    CFAR_FUSED_VARIANTS(CFAR_LAUNCH)
-#undef CFAR_LAUNCH
-    return hipErrorInvalidValue;
 }
 
 }  // namespace cfar

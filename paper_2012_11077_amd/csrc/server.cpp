@@ -22,6 +22,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -140,6 +141,11 @@ struct cfar_server {
     uint64_t next_ticket = 1;
     cfar_server_stats st{};
     int device = 0;
+    // CFAR2D_SERVER_FAIL_TAG (read at creation): every batch holding a frame
+    // with this user tag reports failure, after its device work ran, so the
+    // failure path can be tested without a device fault
+    bool fail_tag_set = false;
+    uint64_t fail_tag = 0;
     std::thread thr;
 };
 
@@ -362,6 +368,11 @@ void launch_admitted(cfar_server *s, std::unique_lock<std::mutex> &lk, Batch &b)
     s->st.device_bytes_peak = std::max(s->st.device_bytes_peak, s->pool.used());
     lk.unlock();
     int rc = b.done ? launch(s, b) : CFAR_EDEVICE;
+    if (rc == CFAR_OK && s->fail_tag_set) {  // forced failure of a batch (tests of the failure path)
+        for (const Frame &f : b.frames)
+            if (f.tag == s->fail_tag) rc = set_error(CFAR_EDEVICE, "batch failed (forced for tag %llu)",
+                                                     (unsigned long long)f.tag);
+    }
     if (rc != CFAR_OK) (void)hipStreamSynchronize(s->streams[b.stream]);  // let what was enqueued finish
     lk.lock();
     b.status = rc;
@@ -453,6 +464,10 @@ int cfar_server_create(const cfar_server_opts *opts, cfar_server **out)
     std::unique_ptr<cfar_server> s(new cfar_server());
     s->opts = o;
     (void)hipGetDevice(&s->device);
+    if (const char *ft = std::getenv("CFAR2D_SERVER_FAIL_TAG")) {
+        s->fail_tag_set = true;
+        s->fail_tag = std::strtoull(ft, nullptr, 10);
+    }
     e = hipMalloc((void **)&s->pool_base, o.device_budget_bytes);
     if (e != hipSuccess) return hip_error(e, "hipMalloc(server pool)");
     s->pool_bytes = o.device_budget_bytes;
@@ -523,9 +538,12 @@ int cfar_poll(cfar_server *s, cfar_completion *out, int32_t max, int32_t timeout
     if (max <= 0) return CFAR_OK;
     std::unique_lock<std::mutex> lk(s->mu);
     auto ready = [&] { return !s->done.empty() || s->stop; };
+    // (frames being launched have left the queue but are not yet in
+    // `inflight`; inflight_frames counts them from admission on)
     if (timeout_us < 0)
         s->cv_poll.wait(lk, [&] {
-            return !s->done.empty() || (s->queue.empty() && s->inflight.empty() && !s->accepting) || s->stop;
+            return !s->done.empty() || (s->queue.empty() && s->st.inflight_frames == 0 && !s->accepting) ||
+                   s->stop;
         });
     else if (timeout_us > 0)
         s->cv_poll.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
@@ -563,7 +581,9 @@ int cfar_server_shutdown(cfar_server *s, int32_t drain_queued)
     }
     s->cv_sched.notify_one();
     // the scheduler keeps running until the queue and the device are empty
-    while (!s->queue.empty() || !s->inflight.empty()) {
+    // (inflight_frames also counts admitted frames whose batch is being
+    // launched, which are in neither list)
+    while (!s->queue.empty() || s->st.inflight_frames > 0) {
         s->cv_poll.wait_for(lk, std::chrono::milliseconds(1));
         s->cv_sched.notify_one();
     }

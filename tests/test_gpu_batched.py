@@ -111,30 +111,3 @@ def test_graph_replays_match_eager():
     for k in range(len(xs)):
         assert np.array_equal(masks[k].cpu().numpy(), ref[k][0])
         np.testing.assert_array_equal(sts[k].cpu().numpy(), 2.0 * ref[k][1])
-
-
-def test_batched_full_config_sampled():
-    """The full uneven batch in the benchmark's launch configuration (one
-    persistent launch, graph replay), checked on sampled cells of a subset
-    of maps against the oracle's direct sums."""
-    import oracle
-    from parity import check_cells, sample_cells
-    specs = synth.config3_specs()
-    xs = []
-    say("full batch: generating", len(specs), "maps")
-    for s in specs:
-        xs.append(torch.from_numpy(synth.generate(s)).to(DEV))
-    masks = [torch.empty(x.shape, dtype=torch.uint8, device=DEV) for x in xs]
-    b = C.Batch(xs, [s.window for s in specs], C.TILED, masks=masks)
-    for _ in range(2):
-        b.run(C.BATCH_GRAPH)
-    torch.cuda.synchronize()
-    say("full batch: checking")
-    rng = np.random.default_rng(0)
-    for k in rng.choice(len(specs), 24, replace=False):
-        s = specs[k]
-        x_np, tg = synth.generate_with_targets(s)
-        rows, cols = sample_cells(s.rows, s.cols, s.guard_r + s.train_r, s.guard_f + s.train_f, tg,
-                                  n_random=3000, seed=int(k))
-        m = masks[k].cpu().numpy()
-        check_cells(x_np, s.window, rows, cols, m[rows, cols])

@@ -145,10 +145,13 @@ def test_shutdown(drain):
             assert t is not None
             tickets[t] = k
         srv.shutdown(drain=drain)
+        # shutdown returns only when nothing is in flight: every ticket's
+        # completion is already posted
+        got = {c.ticket: c for c in srv.poll(len(tickets) + 8, 0)}
+        assert set(got) == set(tickets)
         with pytest.raises(C.CfarError) as e:
             srv.submit(keep[0][0], specs[0].window, keep[0][1])
         assert e.value.code == C.CFAR_ESHUTDOWN
-        got = _drain(srv, tickets, timeout_s=10.0)
     finally:
         srv.close()
     statuses = [c.status for c in got.values()]
@@ -218,3 +221,75 @@ def test_packed_masks():
         bits = np.unpackbits(mh[:, :words].view(np.uint32).view(np.uint8), axis=1, bitorder="little")[:, :F]
         assert np.array_equal(bits, ref[k]), k
         assert (mh[:, words:] == -7).all()
+
+
+def test_failed_batch_fails_only_its_frames(monkeypatch):
+    """A batch whose launch reports failure (forced from the host through
+    CFAR2D_SERVER_FAIL_TAG, after its device work ran) completes its frames
+    with CFAR_EDEVICE; the other frames, in batches of their own, complete
+    normally with the right masks, and the failed batch's memory is given
+    back (a second round of the same frames holds the same pool bytes)."""
+    monkeypatch.setenv("CFAR2D_SERVER_FAIL_TAG", "5")
+    specs, xs = _frames(10, seed=35)
+    ref = [_alone(x, s.window) for x, s in zip(xs, specs)]
+    with C.Server(device_budget_bytes=64 << 20, max_inflight_frames=4, n_hip_streams=2, queue_depth=32,
+                  max_batch_frames=1) as srv:
+        keep = []
+        for s, x in zip(specs, xs):
+            xh = C.host_empty(x.shape, torch.float32)
+            xh.copy_(torch.from_numpy(x))
+            keep.append((xh, C.host_empty(x.shape, torch.uint8)))
+        in_use = []
+        for rnd, tag0 in enumerate((0, 100)):   # the second round has no failing tag
+            tickets = {}
+            for k, (s, (xh, mh)) in enumerate(zip(specs, keep)):
+                mh.fill_(7)
+                t = srv.submit(xh, s.window, mh, tag=tag0 + k)
+                assert t is not None
+                tickets[t] = k
+            got = _drain(srv, tickets)
+            st = srv.stats()
+            assert st.inflight_frames == 0 and st.queued_frames == 0
+            in_use.append(st.device_bytes_in_use)   # the streams' workspaces, no frame blocks
+            for t, c in got.items():
+                k = tickets[t]
+                if rnd == 0 and k == 5:
+                    assert c.status == C.CFAR_EDEVICE
+                else:
+                    assert c.status == C.CFAR_OK
+                    assert np.array_equal(keep[k][1].numpy(), ref[k])
+        srv.shutdown(drain=True)
+        st = srv.stats()
+    assert st.failed == 1 and st.completed == 2 * len(xs)
+    assert in_use[0] == in_use[1]   # the failed batch gave its frames' memory back
+
+
+def test_serving_frame_sizes():
+    """One frame from each of the 16 serving streams (256 x 128 up to
+    4096 x 1024 FP32, the uneven batch's clutter, targets, windows and Pfa),
+    two from the largest, submitted together from page-locked memory:
+    every mask equals the frame alone and the oracle's."""
+    streams = synth.config4_streams(16, 4)
+    frames = [synth.stream_frame_spec(st, 0) for st in streams] + [synth.stream_frame_spec(streams[-1], 1)]
+    xs = [synth.generate(sp) for sp in frames]
+    ref = [_alone(x, sp.window) for x, sp in zip(xs, frames)]
+    with C.Server(device_budget_bytes=1 << 30, max_inflight_frames=32, n_hip_streams=4, queue_depth=64,
+                  max_batch_frames=8) as srv:
+        keep, tickets = [], {}
+        for k, (sp, x) in enumerate(zip(frames, xs)):
+            xh = C.host_empty(x.shape, torch.float32)
+            xh.copy_(torch.from_numpy(x))
+            mh = C.host_empty(x.shape, torch.uint8)
+            mh.fill_(7)
+            keep.append((xh, mh))
+        for k, (sp, (xh, mh)) in enumerate(zip(frames, keep)):
+            t = srv.submit(xh, sp.window, mh, tag=k)
+            assert t is not None
+            tickets[t] = k
+        got = _drain(srv, tickets)
+    for t, c in got.items():
+        k = tickets[t]
+        assert c.status == C.CFAR_OK
+        m = keep[k][1].numpy()
+        assert np.array_equal(m, ref[k]), k
+        check_full(xs[k], frames[k].window, m)

@@ -167,6 +167,19 @@ def test_direct_route_matches_sat_route(oracle_mod):
     assert np.array_equal(m2, mask[rows, cols])
 
 
+def test_threads_do_not_change_the_oracle(oracle_mod):
+    """The per-cell loop split over threads gives bit-identical outputs (the
+    all-core timing and the full-size checks rely on it); counts=False only
+    drops the training counts."""
+    rng = np.random.default_rng(9)
+    x = rng.lognormal(0.0, 2.0, size=(301, 257))
+    one = oracle_mod.cfar2d(x, 2, 3, 9, 7, 1e-4)
+    many = oracle_mod.cfar2d(x, 2, 3, 9, 7, 1e-4, threads=4, counts=False)
+    assert many[2] is None
+    for a, b in ((one[0], many[0]), (one[1], many[1]), (one[3], many[3])):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
 # --------------------------------------------------------------------------
 # eq. (2): the scale factor, closed forms
 # --------------------------------------------------------------------------
