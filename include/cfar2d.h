@@ -184,9 +184,10 @@ int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags,
 typedef struct {
     int32_t k_cols;        /* columns per lane: 2, 4 or 8 (a 64-lane wave covers 64*k_cols cols) */
     int32_t rows_per_unit; /* output rows per work unit, 1..4096                                  */
-    int32_t ring_bytes;    /* 0..65536, or -1 for the library default: accepted for plan tables
-                            * written for earlier kernels, and ignored (the kernel reads every
-                            * row through its own buffer resource and keeps no row ring) */
+    int32_t ring_bytes;    /* LDS bytes per wave for the guard ring, 0..65536, or -1 for the
+                            * library default (12 KiB): the rows r-g_r-1 .. r+g_r of the strip,
+                            * when they fit, so a row step loads three rows instead of five;
+                            * 0 = no ring.  Results do not depend on it. */
 } cfar_plan;
 
 /* The plan the TILED form uses for map m (from the loaded table, else the

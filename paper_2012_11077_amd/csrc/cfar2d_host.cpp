@@ -581,8 +581,7 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
         }
         members[c].push_back(i);
         classes[c].units += (uint32_t)units_of(plans[i]);
-        if (!out)
-            classes[c].ring_bytes = std::max(classes[c].ring_bytes, map_ring_bytes(&maps[i], plans[i]));
+        classes[c].ring_bytes = std::max(classes[c].ring_bytes, map_ring_bytes(&maps[i], plans[i]));
     }
     {
         std::vector<size_t> corder(classes.size());
@@ -692,7 +691,7 @@ static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, si
     a.counter = counter;
     a.total_units = (uint32_t)units;
     a.n_maps = 1;
-    a.ring_bytes = has_outputs(m) ? 0 : map_ring_bytes(m, p);
+    a.ring_bytes = map_ring_bytes(m, p);
     hipError_t e = launch_lut(nullptr, a.single, 1, counter, stream);
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
     e = timing_mark(g_timing.start, stream);

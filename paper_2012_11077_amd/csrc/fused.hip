@@ -44,6 +44,10 @@
 #ifndef CFAR_WAVES
 #define CFAR_WAVES 2
 #endif
+// Guard ring in LDS for the interior rows (when the launch's ring holds it).
+#ifndef CFAR_RING
+#define CFAR_RING 1
+#endif
 
 namespace cfar {
 
@@ -203,7 +207,7 @@ struct Unit {
     double Co[K], Ci[K];
     double z15o = 0.0, z31o = 0.0, z15i = 0.0, z31i = 0.0;
 
-    __device__ __forceinline__ Unit(const MapDesc &d_, int strip, int rchunk, int lane_, double *lds_)
+    __device__ __forceinline__ Unit(const MapDesc &d_, int strip, int rchunk, int lane_, double *lds_, int ring_off)
         : d(d_), lane(lane_)
     {
         R = d.rows;
@@ -236,6 +240,9 @@ struct Unit {
         for (int k = 0; k < K; ++k) beta_col[k] = lut[nt_of(2 * hr + 1, 2 * gr + 1, k)];
         // corner addresses: the outer window's prefix row, then the guard window's
         const uint32_t base = (uint32_t)(size_t)(lds_char *)lds_;
+        // the ring after the prefix rows of the launch's largest k
+        ring0 = base + (uint32_t)ring_off + (uint32_t)lane * (uint32_t)(K * S);
+        asm volatile("" : "+v"(ring0));
         c_oh.init(hf, lane, base);
         c_ol.init(-hf - 1, lane, base);
         c_ih.init(gf, lane, base + BUF);
@@ -317,12 +324,17 @@ struct Unit {
     // corner reads of a row are done before the next row's writes.)
     __device__ __forceinline__ void accumulate_publish(int r, const T (&a)[K], const Rest &s)
     {
+        accumulate_publish(r, a, s.b, s.c, s.e);
+    }
+    __device__ __forceinline__ void accumulate_publish(int r, const T (&a)[K], const T (&b)[K], const T (&c)[K],
+                                                       const T (&e)[K])
+    {
         const double wa = in_map(r + hr, R), wb = in_map(r + gr, R);
         const double wc = -in_map(r - gr - 1, R), we = -in_map(r - hr - 1, R);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            Co[k] = __builtin_fma(we, (double)s.e[k], __builtin_fma(wa, (double)a[k], Co[k]));
-            Ci[k] = __builtin_fma(wc, (double)s.c[k], __builtin_fma(wb, (double)s.b[k], Ci[k]));
+            Co[k] = __builtin_fma(we, (double)e[k], __builtin_fma(wa, (double)a[k], Co[k]));
+            Ci[k] = __builtin_fma(wc, (double)c[k], __builtin_fma(wb, (double)b[k], Ci[k]));
         }
         double po[K], pi[K];
         po[0] = Co[0];
@@ -479,13 +491,111 @@ struct Unit {
         if constexpr (U > 3) if (rem > 2) irow<2>(r + 2, r1, lead, rest);
     }
 
-    __device__ __forceinline__ void run()
+    // The guard ring: the rows r-gr-1 .. r+gr of the strip in LDS (slot of
+    // row i: i mod D, D = 2gr+2), each lane's K values at lane*K*S.  Row r+gr
+    // comes from global memory and goes into the ring; rows r (the cells
+    // under test) and r-gr-1 (leaving the guard window) come back from it, so
+    // a row step loads three rows instead of five.
+    struct RestR {
+        T b[K], e[K];
+    };
+    static constexpr uint32_t RROW = 64u * K * S;  // bytes of one ring row
+    uint32_t ring0;  // LDS byte address of the lane's values in ring slot 0
+    int D;           // ring slots
+    __device__ __forceinline__ void ring_put(int slot, const T (&v)[K]) const
+    {
+        typedef uint32_t r32x4 __attribute__((ext_vector_type(4)));
+        const uint32_t a = ring0 + (uint32_t)slot * RROW;
+#pragma unroll
+        for (int q = 0; q < (int)(K * S / 16); ++q) {
+            r32x4 w;
+            __builtin_memcpy(&w, (const char *)v + 16 * q, 16);
+            *(__attribute__((address_space(3))) r32x4 *)(size_t)(a + 16u * q) = w;
+        }
+        if constexpr (K * S == 8) *(__attribute__((address_space(3))) uint64_t *)(size_t)a = __builtin_bit_cast(uint64_t, v);
+    }
+    __device__ __forceinline__ void ring_get(int slot, T (&v)[K]) const
+    {
+        typedef uint32_t r32x4 __attribute__((ext_vector_type(4)));
+        const uint32_t a = ring0 + (uint32_t)slot * RROW;
+#pragma unroll
+        for (int q = 0; q < (int)(K * S / 16); ++q) {
+            const r32x4 w = *(const __attribute__((address_space(3))) r32x4 *)(size_t)(a + 16u * q);
+            __builtin_memcpy((char *)v + 16 * q, &w, 16);
+        }
+        if constexpr (K * S == 8) {
+            const uint64_t w = *(const __attribute__((address_space(3))) uint64_t *)(size_t)a;
+            __builtin_memcpy(v, &w, 8);
+        }
+    }
+    __device__ __forceinline__ void load_rest(int r, RestR &s) const
+    {
+        ld_row<K, T>(xrow(r + gr), voff, s.b);
+        ld_row<K, T>(xrow(r - hr - 1), voff, s.e);
+    }
+    template <int J>
+    __device__ __forceinline__ void irow_ring(int r, int r1, T (&lead)[PL][K], RestR (&rest)[PD], int &sb, int &su,
+                                              int &sc)
+    {
+        constexpr int JL = J % PL, JR = J % PD;
+        T u[K], c[K];
+        ring_put(sb, rest[JR].b);
+        // the reads below must see that write (the same slot when gr = 0)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ring_get(su, u);
+        ring_get(sc, c);
+        sb = sb + 1 == D ? 0 : sb + 1;
+        su = su + 1 == D ? 0 : su + 1;
+        sc = sc + 1 == D ? 0 : sc + 1;
+        accumulate_publish(r, lead[JL], rest[JR].b, c, rest[JR].e);
+        load_lead(min(r + PL, r1 - 1), lead[JL]);
+        load_rest(min(r + PD, r1 - 1), rest[JR]);
+        Corners cr;
+        corners(cr);
+        decide(r, cr, u, beta_col);
+    }
+    __device__ __forceinline__ void interior_rows_ring(int r0, int r1)
+    {
+        if (r0 >= r1) return;
+        // rows r0-gr-1 .. r0+gr-1 into the ring
+        for (int i = r0 - gr - 1; i < r0 + gr; ++i) {
+            T v[K];
+            ld_row<K, T>(xrow(i), voff, v);
+            ring_put((i % D + D) % D, v);
+        }
+        T lead[PL][K];
+        RestR rest[PD];
+#pragma unroll
+        for (int j = 0; j < PL; ++j) load_lead(min(r0 + j, r1 - 1), lead[j]);
+#pragma unroll
+        for (int j = 0; j < PD; ++j) load_rest(min(r0 + j, r1 - 1), rest[j]);
+        int sb = (r0 + gr) % D, su = r0 % D, sc = (r0 - gr - 1 + D) % D;
+        int r = r0;
+        for (; r + U <= r1; r += U) {
+            irow_ring<0>(r, r1, lead, rest, sb, su, sc);
+            if constexpr (U > 1) irow_ring<1>(r + 1, r1, lead, rest, sb, su, sc);
+            if constexpr (U > 2) irow_ring<2>(r + 2, r1, lead, rest, sb, su, sc);
+            if constexpr (U > 3) irow_ring<3>(r + 3, r1, lead, rest, sb, su, sc);
+        }
+        const int rem = r1 - r;  // < U
+        if constexpr (U > 1) if (rem > 0) irow_ring<0>(r, r1, lead, rest, sb, su, sc);
+        if constexpr (U > 2) if (rem > 1) irow_ring<1>(r + 1, r1, lead, rest, sb, su, sc);
+        if constexpr (U > 3) if (rem > 2) irow_ring<2>(r + 2, r1, lead, rest, sb, su, sc);
+    }
+
+    __device__ __forceinline__ void run(int ring_bytes)
     {
         warm();
         const int i0 = min(max(hr, ra), rb);  // first row whose windows the map does not clip
         const int i1 = max(min(R - hr, rb), i0);
         border_rows(ra, i0);
-        interior_rows(i0, i1);
+        D = 2 * gr + 2;
+        if (CFAR_RING && (uint32_t)D * RROW <= (uint32_t)ring_bytes)  // wave-uniform
+            interior_rows_ring(i0, i1);
+        else
+            interior_rows(i0, i1);
         border_rows(i1, rb);
     }
 };
@@ -527,16 +637,18 @@ fused_kernel(FusedArgs args)
         }
         const int strip = (int)(local % (uint32_t)d.n_strips);
         const int rchunk = (int)(local / (uint32_t)d.n_strips);
+        constexpr int KM = KS == 8 ? 8 : 4;
+        constexpr int ring_off = 2 * KM * 64 * 8;  // after the two prefix rows
         if constexpr (KS == 8) {
-            Unit<8, T, OUT> w(d, strip, rchunk, lane, fused_lds);
-            w.run();
+            Unit<8, T, OUT> w(d, strip, rchunk, lane, fused_lds, ring_off);
+            w.run(args.ring_bytes);
         } else {
             if (d.k_cols == 2) {
-                Unit<2, T, OUT> w(d, strip, rchunk, lane, fused_lds);
-                w.run();
+                Unit<2, T, OUT> w(d, strip, rchunk, lane, fused_lds, ring_off);
+                w.run(args.ring_bytes);
             } else {
-                Unit<4, T, OUT> w(d, strip, rchunk, lane, fused_lds);
-                w.run();
+                Unit<4, T, OUT> w(d, strip, rchunk, lane, fused_lds, ring_off);
+                w.run(args.ring_bytes);
             }
         }
     }
@@ -560,18 +672,19 @@ const void *fused_fn(int kset, int dtype, bool out)
 
 int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes)
 {
-    (void)ring_bytes;
-    constexpr int kDev = 16;
-    static int cached[kDev][8] = {{0}};
+    // cache: device x kernel x ring size (in 512-byte steps)
+    constexpr int kDev = 16, kSteps = 129;
+    static int cached[kDev][8][kSteps] = {{{0}}};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
     const int slot = ((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0);
-    int *c = dev < kDev ? &cached[dev][slot] : nullptr;
+    const int step = ring_bytes % 512 == 0 && ring_bytes / 512 < kSteps ? ring_bytes / 512 : -1;
+    int *c = dev < kDev && step >= 0 ? &cached[dev][slot][step] : nullptr;
     if (c && *c > 0) return *c;
     const void *fn = fused_fn(kset, dtype, out);
     int per_cu = 0, cus = 0;
-    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFusedThreads, fused_lds_bytes(kset, 0)) !=
-                   hipSuccess ||
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kFusedThreads,
+                                                            fused_lds_bytes(kset, ring_bytes)) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     hipDeviceProp_t prop;
@@ -583,11 +696,11 @@ int fused_resident_blocks(int kset, int dtype, bool out, int ring_bytes)
 
 hipError_t launch_fused(const FusedArgs &args, int kset, int dtype, bool out, hipStream_t stream)
 {
-    const int resident = fused_resident_blocks(kset, dtype, out, 0);
+    const int resident = fused_resident_blocks(kset, dtype, out, args.ring_bytes);
     uint32_t blocks = args.total_units;
     if (blocks > (uint32_t)resident) blocks = (uint32_t)resident;
     if (blocks == 0) blocks = 1;
-    const size_t lds = fused_lds_bytes(kset, 0);
+    const size_t lds = fused_lds_bytes(kset, args.ring_bytes);
 #define CFAR_LAUNCH(K_, T_, O_)                                                                                \
     if (kset == K_ && dtype == (sizeof(T_) == 4 ? 0 : 1) && out == O_) {                                       \
         hipLaunchKernelGGL((fused_kernel<K_, T_, O_>), dim3(blocks), dim3(kFusedThreads), lds, stream, args); \

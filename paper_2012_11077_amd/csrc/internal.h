@@ -147,24 +147,21 @@ inline int ring_rows_cap(int k, int dtype, int ring_bytes)
     return cap < kMaxRingRows ? cap : kMaxRingRows;
 }
 
-// Ring bytes one map needs under a budget: every window row (2*hr+2 rows,
-// one global load per step) if they fit, else the guard rows (2*gr+2 rows,
-// three loads per step) if those fit, else none (five loads per step).
+// Ring bytes one map needs under a budget: the guard rows (2*gr+2 rows of
+// the strip; three global loads per row step instead of five) if they fit,
+// else none.
 inline int ring_bytes_needed(int k, int dtype, int hr, int gr, int budget)
 {
-    const int cap = ring_rows_cap(k, dtype, budget);
+    (void)hr;
     const int row = 64 * k * (dtype == 0 ? 4 : 8);
-    if (2 * hr + 2 <= cap) return (2 * hr + 2) * row;
-    if (2 * gr + 2 <= cap) return (2 * gr + 2) * row;
-    return 0;
+    return 2 * gr + 2 <= ring_rows_cap(k, dtype, budget) ? (2 * gr + 2) * row : 0;
 }
 
 // Dynamic LDS of one wave of the TILED kernel: the outer and the guard
-// prefix row, 64*kmax doubles each (no row ring: ring_bytes is ignored).
+// prefix row, 64*kmax doubles each, then the guard ring of the launch.
 inline size_t fused_lds_bytes(int kset, int ring_bytes)
 {
-    (void)ring_bytes;
-    return (size_t)2 * kmax_of(kset) * 64 * 8;
+    return (size_t)2 * kmax_of(kset) * 64 * 8 + (size_t)ring_bytes;
 }
 
 }  // namespace cfar
