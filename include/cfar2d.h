@@ -155,6 +155,21 @@ size_t cfar_workspace_bytes(const cfar_map *maps, int32_t n, int32_t form);
  * wide for the form), CFAR_ENOSPC, CFAR_EDEVICE. */
 int cfar2d(const cfar_map *m, int32_t form, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cfar2d in
+ * the TILED form with its workspace (work counter and threshold table) in a
+ * static device array of cfar2d_static_max_bytes() bytes that each GPU holds
+ * until the process ends, instead of caller memory.  m as in cfar2d.  It
+ * allocates nothing.  Every call on one GPU shares that GPU's array: calls
+ * whose work overlaps on the device (different streams, or host threads)
+ * race and must be ordered by the caller; the array keeps the last call's
+ * contents, and the counter it needs zeroed is cleared by a kernel of the
+ * call itself.  Results are those of cfar2d with CFAR_FORM_TILED.
+ * Errors: as cfar2d; CFAR_ENOSPC when the window's threshold table does not
+ * fit (more than (cfar2d_static_max_bytes() - 256) / 8 - 1 training cells). */
+int cfar2d_static(const cfar_map *m, void *stream);
+size_t cfar2d_static_max_bytes(void);
+
 /* Batch flags. */
 enum {
     CFAR_BATCH_GRAPH = 1  /* capture the launch sequence in a hipGraph and replay it when

@@ -102,6 +102,9 @@ def lib():
         L.cfar_workspace_bytes.restype = _sz
         L.cfar2d.argtypes = [_PMap, _i32, _vp, _sz, _vp]
         L.cfar2d_batched.argtypes = [_PMap, _i32, _i32, _i32, _vp, _sz, _vp]
+        L.cfar2d_static.argtypes = [_PMap, _vp]
+        L.cfar2d_static_max_bytes.argtypes = []
+        L.cfar2d_static_max_bytes.restype = _sz
         L.cfar_plan_for.argtypes = [_PMap, ctypes.POINTER(Plan)]
         L.cfar_plan_load.argtypes = [ctypes.c_char_p]
         L.cfar2d_with_plan.argtypes = [_PMap, ctypes.POINTER(Plan), _vp, _sz, _vp]
@@ -124,7 +127,7 @@ def lib():
         L.cfar_mask_pack.argtypes = [_PMap, _vp, _i64, _vp]
         L.cfar_timing_enable.argtypes = [_i32]
         L.cfar_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double)]
-        for name in ("sat2d", "cfar2d", "cfar2d_batched", "cfar_plan_for", "cfar_plan_load",
+        for name in ("sat2d", "cfar2d", "cfar2d_static", "cfar2d_batched", "cfar_plan_for", "cfar_plan_load",
                      "cfar2d_with_plan", "cfar_timing_enable", "cfar_timing_read", "cfar_server_create",
                      "cfar_submit", "cfar_poll", "cfar_server_stats_get", "cfar_server_shutdown",
                      "cfar_server_destroy", "cfar_host_alloc", "cfar_host_free", "cfar_detections",
@@ -274,6 +277,15 @@ def cfar2d(x: torch.Tensor, window, form: int = TILED, mask: Optional[torch.Tens
     if ws is None:
         ws = _alloc_ws(workspace_bytes([m], form), x.device)
     _check(lib().cfar2d(ctypes.byref(m), form, ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+    return mask
+
+
+def cfar2d_static(x: torch.Tensor, window, mask: torch.Tensor, train_sum: Optional[torch.Tensor] = None,
+                  threshold: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """TILED CA-CFAR over one map with the library's static device workspace
+    (allocates nothing; the caller passes the outputs)."""
+    m = make_map(x, window, mask, train_sum, threshold)
+    _check(lib().cfar2d_static(ctypes.byref(m), _stream_handle(stream)))
     return mask
 
 
