@@ -47,9 +47,13 @@ def log(*a):
 
 
 def kernel_source_sha() -> str:
-    p = os.path.join(ROOT, "paper_2012_11077_amd", "csrc", "kernels.hip")
-    with open(p, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources that decide the fused kernel's memory traffic: the
+    kernel, its descriptor layout and the host planner."""
+    h = hashlib.sha256()
+    for name in ("fused.hip", "internal.h", "cfar2d_host.cpp"):
+        with open(os.path.join(ROOT, "paper_2012_11077_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload):

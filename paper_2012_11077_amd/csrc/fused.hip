@@ -32,14 +32,19 @@
 #include <type_traits>
 
 // Rows of loads in flight in the interior loop: of the lead row (CFAR_PL)
-// and of the other four rows (CFAR_PD); waves per SIMD the FP32 kernel's
-// registers aim at (CFAR_WAVES).  Measured on the uneven batch: the far
-// re-read rows dominate, and depth beats occupancy (4 / 4 at 2 waves).
+// and of the other four rows (CFAR_PD) without the guard ring, of the two
+// rows still read from memory (CFAR_PDR) with it; waves per SIMD the FP32
+// kernel's registers aim at (CFAR_WAVES).  Measured on the uneven batch:
+// depth beats occupancy (2 waves per SIMD), and the ring loop gains from
+// eight rows of the far rows in flight (2.67 ms against 2.73 ms at four).
 #ifndef CFAR_PD
 #define CFAR_PD 4
 #endif
 #ifndef CFAR_PL
 #define CFAR_PL 4
+#endif
+#ifndef CFAR_PDR
+#define CFAR_PDR 8
 #endif
 #ifndef CFAR_WAVES
 #define CFAR_WAVES 2
@@ -87,21 +92,21 @@ struct Rows {
     }
 };
 
-// K consecutive values of one row at lane byte offset voff (plus the
-// wave-uniform byte offset soff, which the range check leaves out).
+// K consecutive values of one row at lane byte offset voff (each dword past
+// the resource's size reads as zero).
 template <int K, typename T>
-__device__ __forceinline__ void ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, T (&v)[K], uint32_t soff = 0u)
+__device__ __forceinline__ void ld_row(__amdgpu_buffer_rsrc_t rs, uint32_t voff, T (&v)[K])
 {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     if constexpr (K * sizeof(T) == 8) {
-        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+        const u32x2 w = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0u, 0));
         __builtin_memcpy(v, &w, 8);
     } else {
 #pragma unroll
         for (int q = 0; q < (int)(K * sizeof(T) / 16); ++q) {
             const u32x4 w =
-                __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16u * q, soff, 0));
+                __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16u * q, 0u, 0));
             __builtin_memcpy((char *)v + 16 * q, &w, 16);
         }
     }
@@ -186,8 +191,12 @@ struct Unit {
     // rows of loads in flight: of the lead row (new data), of the other rows
     static constexpr int PL = K * S >= 32 ? 1 : CFAR_PL;
     static constexpr int PD = K * S >= 32 ? 1 : CFAR_PD;
-    static constexpr int U = PL > PD ? PL : PD;  // loop unroll
-    static_assert((PL == 1 || PL == 2 || PL == 4) && (PD == 1 || PD == 2 || PD == 4), "slots rotate by powers of 2");
+    static constexpr int PDR = K * S >= 32 ? 1 : CFAR_PDR;  // the ring loop's other rows (two per step)
+    static constexpr int U = PL > PD ? PL : PD;      // loop unroll
+    static constexpr int UR = PL > PDR ? PL : PDR;   // loop unroll with the ring
+    static_assert((PL == 1 || PL == 2 || PL == 4 || PL == 8) && (PD == 1 || PD == 2 || PD == 4 || PD == 8) &&
+                      (PDR == 1 || PDR == 2 || PDR == 4 || PDR == 8),
+                  "slots rotate by powers of 2");
 
     const MapDesc &d;
     const int lane;
@@ -429,6 +438,25 @@ struct Unit {
             }
         }
     }
+    // Rows [r, r1) through f(slot, row), slots 0..U-1 in turn: full rounds of
+    // U rows, then the remaining rows of a last round.
+    template <int UU, typename Fn>
+    __device__ __forceinline__ void unrolled_rows(int r, int r1, Fn &f)
+    {
+        for (; r + UU <= r1; r += UU) round<0, UU>(r, r1, f);
+        round<0, UU>(r, r1, f);  // < UU rows left
+    }
+    template <int J, int UU, typename Fn>
+    __device__ __forceinline__ void round(int r, int r1, Fn &f)
+    {
+        if constexpr (J < UU) {
+            if (r + J < r1) {  // wave-uniform; always true in full rounds
+                f(std::integral_constant<int, J>(), r + J);
+                round<J + 1, UU>(r, r1, f);
+            }
+        }
+    }
+
     // Rows whose windows the map clips (within hr of the top or bottom):
     // one after the other, the factors from the table per cell.
     __device__ __forceinline__ void border_rows(int r0, int r1)
@@ -479,16 +507,8 @@ struct Unit {
 #pragma unroll
         for (int j = 0; j < PD; ++j) load_rest(min(r0 + j, r1 - 1), rest[j]);
         int r = r0;
-        for (; r + U <= r1; r += U) {
-            irow<0>(r, r1, lead, rest);
-            if constexpr (U > 1) irow<1>(r + 1, r1, lead, rest);
-            if constexpr (U > 2) irow<2>(r + 2, r1, lead, rest);
-            if constexpr (U > 3) irow<3>(r + 3, r1, lead, rest);
-        }
-        const int rem = r1 - r;  // < U
-        if constexpr (U > 1) if (rem > 0) irow<0>(r, r1, lead, rest);
-        if constexpr (U > 2) if (rem > 1) irow<1>(r + 1, r1, lead, rest);
-        if constexpr (U > 3) if (rem > 2) irow<2>(r + 2, r1, lead, rest);
+        auto one = [&](auto jt, int rr) { irow<decltype(jt)::value>(rr, r1, lead, rest); };
+        unrolled_rows<U>(r, r1, one);
     }
 
     // The guard ring: the rows r-gr-1 .. r+gr of the strip in LDS (slot of
@@ -534,10 +554,10 @@ struct Unit {
         ld_row<K, T>(xrow(r - hr - 1), voff, s.e);
     }
     template <int J>
-    __device__ __forceinline__ void irow_ring(int r, int r1, T (&lead)[PL][K], RestR (&rest)[PD], int &sb, int &su,
+    __device__ __forceinline__ void irow_ring(int r, int r1, T (&lead)[PL][K], RestR (&rest)[PDR], int &sb, int &su,
                                               int &sc)
     {
-        constexpr int JL = J % PL, JR = J % PD;
+        constexpr int JL = J % PL, JR = J % PDR;
         T u[K], c[K];
         ring_put(sb, rest[JR].b);
         // the reads below must see that write (the same slot when gr = 0)
@@ -551,7 +571,7 @@ struct Unit {
         sc = sc + 1 == D ? 0 : sc + 1;
         accumulate_publish(r, lead[JL], rest[JR].b, c, rest[JR].e);
         load_lead(min(r + PL, r1 - 1), lead[JL]);
-        load_rest(min(r + PD, r1 - 1), rest[JR]);
+        load_rest(min(r + PDR, r1 - 1), rest[JR]);
         Corners cr;
         corners(cr);
         decide(r, cr, u, beta_col);
@@ -566,23 +586,15 @@ struct Unit {
             ring_put((i % D + D) % D, v);
         }
         T lead[PL][K];
-        RestR rest[PD];
+        RestR rest[PDR];
 #pragma unroll
         for (int j = 0; j < PL; ++j) load_lead(min(r0 + j, r1 - 1), lead[j]);
 #pragma unroll
-        for (int j = 0; j < PD; ++j) load_rest(min(r0 + j, r1 - 1), rest[j]);
+        for (int j = 0; j < PDR; ++j) load_rest(min(r0 + j, r1 - 1), rest[j]);
         int sb = (r0 + gr) % D, su = r0 % D, sc = (r0 - gr - 1 + D) % D;
         int r = r0;
-        for (; r + U <= r1; r += U) {
-            irow_ring<0>(r, r1, lead, rest, sb, su, sc);
-            if constexpr (U > 1) irow_ring<1>(r + 1, r1, lead, rest, sb, su, sc);
-            if constexpr (U > 2) irow_ring<2>(r + 2, r1, lead, rest, sb, su, sc);
-            if constexpr (U > 3) irow_ring<3>(r + 3, r1, lead, rest, sb, su, sc);
-        }
-        const int rem = r1 - r;  // < U
-        if constexpr (U > 1) if (rem > 0) irow_ring<0>(r, r1, lead, rest, sb, su, sc);
-        if constexpr (U > 2) if (rem > 1) irow_ring<1>(r + 1, r1, lead, rest, sb, su, sc);
-        if constexpr (U > 3) if (rem > 2) irow_ring<2>(r + 2, r1, lead, rest, sb, su, sc);
+        auto one = [&](auto jt, int rr) { irow_ring<decltype(jt)::value>(rr, r1, lead, rest, sb, su, sc); };
+        unrolled_rows<UR>(r, r1, one);
     }
 
     __device__ __forceinline__ void run(int ring_bytes)
