@@ -290,26 +290,41 @@ struct Unit {
     // Column sums before the first output row ra: Co over rows ra-hr-1 ..
     // ra+hr-1, Ci over rows ra-gr-1 .. ra+gr-1, so that the first step, like
     // every later one, adds rows r+hr, r+gr and takes off rows r-hr-1, r-gr-1.
-    __device__ __forceinline__ void warm()
+    // Two batches of rows in flight (the loads of the next batch are issued
+    // before the current one is summed); with fill set, the rows of the guard
+    // window (ra-gr-1 .. ra+gr-1) also go into the guard ring.
+    __device__ __forceinline__ void warm(bool fill)
     {
         constexpr int WB = K * S >= 32 ? 4 : 8;
         const int w0 = ra - hr - 1, w1 = ra + hr;  // [w0, w1)
         const int g0 = ra - gr - 1, g1 = ra + gr;
-        for (int i0 = w0; i0 < w1; i0 += WB) {
-            T v[WB][K];
+        T v[2][WB][K];
+        // rows past w1 - 1 load that row again (a cache hit; never summed)
+        auto issue = [&](T (&b)[WB][K], int i0) {
 #pragma unroll
-            for (int j = 0; j < WB; ++j) ld_row<K, T>(xrow(i0 + j), voff, v[j]);
+            for (int j = 0; j < WB; ++j) ld_row<K, T>(xrow(min(i0 + j, w1 - 1)), voff, b[j]);
+        };
+        auto take = [&](const T (&b)[WB][K], int i0) {
 #pragma unroll
             for (int j = 0; j < WB; ++j) {
                 const int i = i0 + j;
+                const bool guard = i >= g0 && i < g1;  // wave-uniform
                 const double wo = i < w1 ? in_map(i, R) : 0.0;
-                const double wi = (i >= g0 && i < g1) ? wo : 0.0;
+                const double wi = guard ? wo : 0.0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    Co[k] = __builtin_fma(wo, (double)v[j][k], Co[k]);
-                    Ci[k] = __builtin_fma(wi, (double)v[j][k], Ci[k]);
+                    Co[k] = __builtin_fma(wo, (double)b[j][k], Co[k]);
+                    Ci[k] = __builtin_fma(wi, (double)b[j][k], Ci[k]);
                 }
+                if (fill && guard) ring_put(ring_slot(i), b[j]);
             }
+        };
+        issue(v[0], w0);
+        for (int i0 = w0; i0 < w1; i0 += 2 * WB) {
+            issue(v[1], i0 + WB);
+            take(v[0], i0);
+            issue(v[0], i0 + 2 * WB);
+            take(v[1], i0 + WB);
         }
     }
 
@@ -576,15 +591,24 @@ struct Unit {
         corners(cr);
         decide(r, cr, u, beta_col);
     }
-    __device__ __forceinline__ void interior_rows_ring(int r0, int r1)
+    // Rows r0-gr-1 .. r0+gr-1 into the guard ring, four loads in flight.
+    __device__ __forceinline__ void fill_ring(int r0)
+    {
+        for (int i0 = r0 - gr - 1; i0 < r0 + gr; i0 += 4) {
+            T v[4][K];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) ld_row<K, T>(xrow(min(i0 + j, r0 + gr - 1)), voff, v[j]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (i0 + j < r0 + gr) ring_put(ring_slot(i0 + j), v[j]);
+        }
+    }
+    __device__ __forceinline__ int ring_slot(int i) const { return (i % D + D) % D; }
+    // filled: the ring already holds rows r0-gr-1 .. r0+gr-1 (from warm()).
+    __device__ __forceinline__ void interior_rows_ring(int r0, int r1, bool filled)
     {
         if (r0 >= r1) return;
-        // rows r0-gr-1 .. r0+gr-1 into the ring
-        for (int i = r0 - gr - 1; i < r0 + gr; ++i) {
-            T v[K];
-            ld_row<K, T>(xrow(i), voff, v);
-            ring_put((i % D + D) % D, v);
-        }
+        if (!filled) fill_ring(r0);
         T lead[PL][K];
         RestR rest[PDR];
 #pragma unroll
@@ -599,13 +623,14 @@ struct Unit {
 
     __device__ __forceinline__ void run(int ring_bytes)
     {
-        warm();
         const int i0 = min(max(hr, ra), rb);  // first row whose windows the map does not clip
         const int i1 = max(min(R - hr, rb), i0);
-        border_rows(ra, i0);
         D = 2 * gr + 2;
-        if (CFAR_RING && (uint32_t)D * RROW <= (uint32_t)ring_bytes)  // wave-uniform
-            interior_rows_ring(i0, i1);
+        const bool ring = CFAR_RING && i0 < i1 && (uint32_t)D * RROW <= (uint32_t)ring_bytes;  // wave-uniform
+        warm(ring && i0 == ra);
+        border_rows(ra, i0);
+        if (ring)
+            interior_rows_ring(i0, i1, i0 == ra);
         else
             interior_rows(i0, i1);
         border_rows(i1, rb);
