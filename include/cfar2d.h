@@ -62,7 +62,13 @@ typedef enum { CFAR_F32 = 0, CFAR_F64 = 1 } cfar_dtype;
 
 /* Precision forms.
  *   PLAIN: the integral image of eq. (3) is materialised in FP64 in device
- *          memory (by sat2d), then the eight-corner stencil of eq. (4) reads it.
+ *          memory, then the eight-corner stencil of eq. (4) reads it back.  The
+ *          image is built by work units of 64 rows x 256 columns (per-unit row
+ *          and column totals, their exclusive scans across units, then each
+ *          unit's own prefix sums plus those carries); the stencil takes the
+ *          four corner rows of a cell's outer and guard windows from it, their
+ *          per-column differences, and the column corners of those.  Any
+ *          window size (guard_f + train_f above 247 takes a per-cell stencil).
  *   TILED: the integral image is never materialised.  The eight corners of
  *          eq. (4) are separable: each work unit (a strip of columns plus a
  *          halo of guard_f + train_f + 1 columns, times a chunk of rows)
@@ -122,7 +128,7 @@ typedef struct {
  * Returns 0 when rows or cols < 1. */
 size_t sat2d_bytes(int64_t rows, int64_t cols, int32_t form);
 
-/* Bytes of device workspace sat2d needs (tile aggregates and carries). */
+/* Bytes of device workspace sat2d needs (unit aggregates and carries). */
 size_t sat2d_workspace_bytes(int64_t rows, int64_t cols, int32_t form);
 
 /* Integral image of X (eq. 3) in the layout of `form` (see sat2d_bytes).
@@ -139,9 +145,9 @@ int sat2d(const void *x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, 
 /* ------------------------------------------------------------------------ */
 
 /* Device workspace bytes for cfar2d / cfar2d_batched over `n` maps in `form`
- * (PLAIN: the FP64 SAT of the largest map plus its aggregates, plus the
- * threshold tables; TILED: descriptors, work counters and threshold tables;
- * DIRECT: the largest map's threshold table).
+ * (PLAIN: for every map its FP64 integral image, the carries and the
+ * threshold table, plus the descriptors when n > 1; TILED: descriptors, work
+ * counters and threshold tables; DIRECT: the largest map's threshold table).
  * Returns 0 when an argument is invalid (cfar_last_error() says which). */
 size_t cfar_workspace_bytes(const cfar_map *maps, int32_t n, int32_t form);
 
@@ -185,7 +191,11 @@ enum {
  * library's own streams forked from and joined back into `stream`.  Each
  * map's tile plan depends only on that map's own size, window and dtype, so
  * every map's result is the same alone and in any batch.
- * PLAIN: the per-map FP64 form, one sat2d + stencil per map on `stream`.
+ * PLAIN: the FP64 integral images of all maps, then their stencils, in five
+ * launches on `stream` for the whole batch (threshold tables, unit totals,
+ * carries, integral images, stencil), plus one per-cell stencil launch per
+ * map wider than the strip stencil holds; flags other than 0 are accepted
+ * and ignored.
  * DIRECT: one table + direct-sum stencil per map on `stream` (flags other
  * than 0 are accepted and ignored).
  * Errors as cfar2d; map k's problems are reported with its index. */

@@ -216,7 +216,7 @@ def sat2d(x: torch.Tensor, form: int = PLAIN, out: Optional[torch.Tensor] = None
           ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Integral image (eq. 3) of ``x``.  PLAIN: returns an R x F float64
     tensor.  TILED: returns the raw byte buffer of the tiled layout (see
-    include/cfar2d.h; :func:`decode_tiled_sat` rebuilds S from it)."""
+    include/cfar2d.h)."""
     _check_2d(x, "x")
     L = lib()
     R, F = x.shape
@@ -233,30 +233,6 @@ def sat2d(x: torch.Tensor, form: int = PLAIN, out: Optional[torch.Tensor] = None
                    out.numel() * out.element_size(), ws.data_ptr(), ws.numel(),
                    _stream_handle(stream)))
     return out
-
-
-def decode_tiled_sat(buf: torch.Tensor, rows: int, cols: int) -> torch.Tensor:
-    """S(i,j) from the TILED sat2d layout, as float64 (done on the tensor's
-    device with torch ops: a readback helper, not part of the hot path)."""
-    line = 32
-
-    def up(v):
-        return (v + 255) // 256 * 256
-
-    nI, nJ = (rows + line - 1) // line, (cols + line - 1) // line
-    loc_b = up(rows * cols * 4)
-    row_b = up(nI * cols * 8)
-    raw = buf.view(torch.uint8)
-    loc = raw[:rows * cols * 4].view(torch.float32).view(rows, cols).double()
-    rowline = raw[loc_b:loc_b + nI * cols * 8].view(torch.float64).view(nI, cols)
-    colline = raw[loc_b + row_b:loc_b + row_b + nJ * rows * 8].view(torch.float64).view(nJ, rows)
-    I = torch.arange(rows, device=buf.device) // line
-    J = torch.arange(cols, device=buf.device) // line
-    top = rowline[I][:, :]                      # rows x cols: S(32I-1, j)
-    left = colline[J][:, :].t()                 # rows x cols: S(i, 32J-1)
-    cj = (J * line - 1).clamp(min=0)
-    corner = rowline[I][:, cj] * (J > 0).double()[None, :]
-    return top + left - corner + loc
 
 
 def workspace_bytes(maps: Sequence[Map], form: int) -> int:

@@ -284,9 +284,114 @@ static MapDesc make_desc(const cfar_map *m, const Plan *p, double *lut)
 // ---------------------------------------------------------------------------
 // Workspace layouts
 // ---------------------------------------------------------------------------
-static size_t plain_single_ws(const cfar_map *m)
+// PLAIN form: integral-image units of kPlainChunk rows x kPlainW columns;
+// stencil units of kPlainBand rows of one strip of 64*st_k columns.
+constexpr int kPlainChunk = 128;
+constexpr int kPlainBand = 16;
+
+// Rows per unit of the PLAIN form's kernels (CFAR2D_PLAIN_CHUNK and
+// CFAR2D_PLAIN_BAND override the defaults, for tuning).
+static int env_or(const char *name, int dflt)
 {
-    return align_up((size_t)m->rows * (size_t)m->cols * 8, 256) + sat_ws_bytes(m->rows, m->cols) + lut_bytes(m);
+    const char *e = std::getenv(name);
+    const int v = e ? std::atoi(e) : 0;
+    return v > 0 ? v : dflt;
+}
+static int plain_chunk()
+{
+    static const int v = env_or("CFAR2D_PLAIN_CHUNK", kPlainChunk);
+    return v;
+}
+static int plain_band()
+{
+    static const int v = env_or("CFAR2D_PLAIN_BAND", kPlainBand);
+    return v;
+}
+static int plain_xcd()
+{
+    static const int v = env_or("CFAR2D_PLAIN_XCD", 2) - 1;  // 1 (default): XCD-grouped stencil units
+    return v;
+}
+
+static void plain_geometry(const cfar_map *m, PlainDesc &d)
+{
+    std::memset(&d, 0, sizeof d);
+    const int64_t R = m->rows, F = m->cols;
+    d.chunk = (int32_t)std::min<int64_t>(plain_chunk(), R);
+    d.n_chunks = (int32_t)((R + d.chunk - 1) / d.chunk);
+    d.n_strips = (int32_t)((F + kPlainW - 1) / kPlainW);
+    const int hf = m->win.guard_f + m->win.train_f;
+    // k = 4 while the halo costs less than half the strip, k = 8 up to the
+    // widest window a 512-column strip holds, else the per-cell stencil
+    d.st_k = hf <= 60 ? 4 : hf <= kMaxTiledHf ? 8 : 0;
+    if (d.st_k) {
+        const int a = std::max(4, (int)d.st_k);
+        d.st_halo = (hf + 1 + a - 1) / a * a;
+        d.st_tw = 64 * d.st_k - 2 * d.st_halo;
+        d.st_strips = (int32_t)((F + d.st_tw - 1) / d.st_tw);
+        d.st_band = (int32_t)std::min<int64_t>(plain_band(), R);
+        d.st_bands = (int32_t)((R + d.st_band - 1) / d.st_band);
+        // maps of 8 strips or more: unit u of a band goes to strip group
+        // u mod 8, so that the waves of one XCD (workgroups are dealt to the
+        // XCDs in turn) keep to one group of columns and share its rows in L2
+        if (plain_xcd() && d.st_strips >= 8) d.st_xcd = (d.st_strips + 7) / 8;
+    }
+}
+
+static uint64_t plain_sat_units(const PlainDesc &d) { return (uint64_t)d.n_chunks * (uint64_t)d.n_strips; }
+static uint64_t plain_st_units(const PlainDesc &d)
+{
+    if (!d.st_k) return 0;
+    // a multiple of 8, so that every map's units start on the same XCD
+    const uint64_t n = (uint64_t)d.st_bands * (uint64_t)(d.st_xcd ? 8 * d.st_xcd : d.st_strips);
+    return (n + 7) / 8 * 8;
+}
+static uint64_t plain_carry_blocks(const cfar_map *m) { return (uint64_t)((m->cols + 255) / 256 + (m->rows + 255) / 256); }
+
+// Device memory of the PLAIN form: a head (descriptors and unit tables,
+// copied from the host; none for one map), then per map the integral image,
+// the row carries, the column carries and the threshold table.
+struct PlainLayout {
+    size_t head_bytes = 0, off_desc = 0, off_sat = 0, off_st = 0, off_blk = 0;
+    std::vector<size_t> s_off, left_off, v_off, lut_off;
+    size_t total = 0;
+};
+
+static PlainLayout plain_layout(const cfar_map *maps, int n, std::vector<PlainDesc> &pd)
+{
+    PlainLayout L;
+    pd.resize(n);
+    if (n > 1) {
+        L.off_desc = 0;
+        L.off_sat = (size_t)n * sizeof(PlainDesc);
+        L.off_st = L.off_sat + align_up((size_t)(n + 1) * 4, 16);
+        L.off_blk = L.off_st + align_up((size_t)(n + 1) * 4, 16);
+        L.head_bytes = align_up(L.off_blk + (size_t)(n + 1) * 4, 256);
+    }
+    size_t off = L.head_bytes;
+    L.s_off.resize(n);
+    L.left_off.resize(n);
+    L.v_off.resize(n);
+    L.lut_off.resize(n);
+    for (int i = 0; i < n; ++i) {
+        plain_geometry(&maps[i], pd[i]);
+        L.s_off[i] = off;
+        off += align_up((size_t)maps[i].rows * (size_t)maps[i].cols * 8, 256);
+        L.left_off[i] = off;
+        off += align_up((size_t)pd[i].n_strips * (size_t)maps[i].rows * 8, 256);
+        L.v_off[i] = off;
+        off += align_up((size_t)pd[i].n_chunks * (size_t)maps[i].cols * 8, 256);
+        L.lut_off[i] = off;
+        off += lut_bytes(&maps[i]);
+    }
+    L.total = off;
+    return L;
+}
+
+static size_t plain_ws_bytes(const cfar_map *maps, int n)
+{
+    std::vector<PlainDesc> pd;
+    return plain_layout(maps, n, pd).total;
 }
 
 struct TiledLayout {
@@ -499,7 +604,7 @@ static int enqueue_tiled_batch(BatchCtx *ctx, const Slot &sl, const TiledLayout 
     std::memset(&dummy, 0, sizeof dummy);
     const MapDesc *descs = (const MapDesc *)(ws + L.off_desc);
     BatchHeader *hdr = (BatchHeader *)ws;
-    e = launch_lut(descs, dummy, (int)n, hdr->counter, stream);
+    e = launch_lut(descs, sizeof(MapDesc), dummy, (int)n, hdr->counter, stream);
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
     e = timing_mark(g_timing.start, stream);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
@@ -692,7 +797,7 @@ static int run_tiled_single(const cfar_map *m, const cfar_plan &cp, void *ws, si
     a.total_units = (uint32_t)units;
     a.n_maps = 1;
     a.ring_bytes = map_ring_bytes(m, p);
-    hipError_t e = launch_lut(nullptr, a.single, 1, counter, stream);
+    hipError_t e = launch_lut(nullptr, 0, a.single, 1, counter, stream);
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
     e = timing_mark(g_timing.start, stream);
     if (e != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
@@ -723,7 +828,7 @@ static int run_direct_single(const cfar_map *m, void *ws, size_t ws_bytes, hipSt
     if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
     if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
     MapDesc d = make_desc(m, nullptr, (double *)ws);
-    hipError_t e = launch_lut(nullptr, d, 1, nullptr, stream);
+    hipError_t e = launch_lut(nullptr, 0, d, 1, nullptr, stream);
     if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
     if (first && (e = timing_mark(g_timing.start, stream)) != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
     e = launch_stencil_direct(d, stream);
@@ -735,25 +840,129 @@ static int run_direct_single(const cfar_map *m, void *ws, size_t ws_bytes, hipSt
     return CFAR_OK;
 }
 
-// Single map, PLAIN: FP64 SAT into ws, table, stencil.
-static int run_plain_single(const cfar_map *m, void *ws, size_t ws_bytes, hipStream_t stream)
+// PLAIN form over n maps: the head (for more than one map) through the
+// pinned staging of the batch context, the threshold tables, then the
+// integral image and the stencil, each one launch over every map's units.
+// Maps too wide for the strip stencil take the per-cell stencil, one launch
+// each.
+static int run_plain_batch(const cfar_map *maps, int n, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    const size_t need = plain_single_ws(m);
-    if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
+    std::vector<PlainDesc> pd;
+    const PlainLayout L = plain_layout(maps, n, pd);
+    if (ws_bytes < L.total) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, L.total);
     if (!ws) return set_error(CFAR_EINVAL, "ws is NULL");
-    char *base = (char *)ws;
-    const size_t sat_b = align_up((size_t)m->rows * (size_t)m->cols * 8, 256);
-    double *sat = (double *)base;
-    SatWs sw = sat_ws_layout(base + sat_b, m->rows, m->cols);
-    double *lut = (double *)(base + sat_b + sat_ws_bytes(m->rows, m->cols));
-    hipError_t e = launch_sat2d(m->x, m->dtype, m->rows, m->cols, m->ld, 0, sat, sw, stream);
-    if (e != hipSuccess) return hip_error(e, "launch(sat2d)");
-    MapDesc d = make_desc(m, nullptr, lut);
-    e = launch_lut(nullptr, d, 1, nullptr, stream);
-    if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
-    e = launch_stencil_plain(d, sat, stream);
-    if (e != hipSuccess) return hip_error(e, "launch(stencil_plain)");
+    char *w = (char *)ws;
+    PlainArgs a;
+    std::memset(&a, 0, sizeof a);
+    uint64_t sat_units = 0, st_units = 0, blocks = 0;
+    int k_mask = 0;
+    bool any_out = false;
+    std::vector<uint32_t> sat_base(n + 1), st_base(n + 1), blk_base(n + 1);
+    for (int i = 0; i < n; ++i) {
+        PlainDesc &d = pd[i];
+        d.m = make_desc(&maps[i], nullptr, (double *)(w + L.lut_off[i]));
+        d.S = (double *)(w + L.s_off[i]);
+        d.left = (double *)(w + L.left_off[i]);
+        d.V = (double *)(w + L.v_off[i]);
+        sat_base[i] = (uint32_t)sat_units;
+        st_base[i] = (uint32_t)st_units;
+        blk_base[i] = (uint32_t)blocks;
+        sat_units += plain_sat_units(d);
+        st_units += plain_st_units(d);
+        blocks += plain_carry_blocks(&maps[i]);
+        k_mask |= d.st_k;
+        any_out = any_out || (d.st_k && has_outputs(&maps[i]));
+    }
+    if (sat_units >= (uint64_t)1 << 31 || st_units >= (uint64_t)1 << 31 || blocks >= (uint64_t)1 << 31)
+        return set_error(CFAR_EINVAL, "batch has too many work units");
+    sat_base[n] = (uint32_t)sat_units;
+    st_base[n] = (uint32_t)st_units;
+    blk_base[n] = (uint32_t)blocks;
+    a.n_maps = (uint32_t)n;
+    a.sat_units = (uint32_t)sat_units;
+    a.st_units = (uint32_t)st_units;
+    a.carry_blocks = (uint32_t)blocks;
+    hipError_t e;
+    if (n == 1) {
+        a.single = pd[0];
+        e = launch_lut(nullptr, 0, pd[0].m, 1, nullptr, stream);
+        if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
+    } else {
+        BatchCtx *ctx = get_ctx(stream, ws);
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        Slot &sl = ctx->slot[ctx->next];
+        ctx->next ^= 1;
+        int rc = slot_reserve(sl, L.head_bytes);
+        if (rc != CFAR_OK) return rc;
+        char *h = (char *)sl.pinned;
+        std::memcpy(h + L.off_desc, pd.data(), (size_t)n * sizeof(PlainDesc));
+        std::memcpy(h + L.off_sat, sat_base.data(), (size_t)(n + 1) * 4);
+        std::memcpy(h + L.off_st, st_base.data(), (size_t)(n + 1) * 4);
+        std::memcpy(h + L.off_blk, blk_base.data(), (size_t)(n + 1) * 4);
+        e = hipMemcpyAsync(ws, sl.pinned, L.head_bytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(descriptors)");
+        e = hipEventRecord(sl.done, stream);
+        if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+        sl.recorded = true;
+        a.descs = (const PlainDesc *)(w + L.off_desc);
+        a.sat_base = (const uint32_t *)(w + L.off_sat);
+        a.st_base = (const uint32_t *)(w + L.off_st);
+        a.blk_base = (const uint32_t *)(w + L.off_blk);
+        MapDesc dummy;
+        std::memset(&dummy, 0, sizeof dummy);
+        e = launch_lut(a.descs, sizeof(PlainDesc), dummy, n, nullptr, stream);
+        if (e != hipSuccess) return hip_error(e, "launch(lut_kernel)");
+    }
+    if ((e = timing_mark(g_timing.start, stream)) != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
+    e = launch_plain(a, k_mask, true, any_out, stream);
+    if (e != hipSuccess) return hip_error(e, "launch(plain)");
+    for (int i = 0; i < n; ++i) {
+        if (pd[i].st_k) continue;
+        e = launch_stencil_plain(pd[i].m, pd[i].S, stream);
+        if (e != hipSuccess) return hip_error(e, "launch(stencil_plain)");
+    }
+    if ((e = timing_mark(g_timing.stop, stream)) != hipSuccess) return hip_error(e, "hipEventRecord(timing)");
+    if (g_timing.on) g_timing.recorded = true;
     return CFAR_OK;
+}
+
+// sat2d, PLAIN form: the integral-image kernels of the PLAIN form on one map
+// (no stencil); ws holds the row and column carries.
+static size_t plain_sat_ws_bytes(int64_t rows, int64_t cols)
+{
+    const int64_t chunk = std::min<int64_t>(plain_chunk(), rows);
+    const int64_t nc = (rows + chunk - 1) / chunk, ns = (cols + kPlainW - 1) / kPlainW;
+    return align_up((size_t)(ns * rows) * 8, 256) + align_up((size_t)(nc * cols) * 8, 256);
+}
+
+static int run_plain_sat2d(const void *x, int dtype, int64_t rows, int64_t cols, int64_t ld, double *sat, void *ws,
+                           hipStream_t stream)
+{
+    PlainArgs a;
+    std::memset(&a, 0, sizeof a);
+    PlainDesc &d = a.single;
+    cfar_map m;
+    std::memset(&m, 0, sizeof m);
+    m.x = x;
+    m.dtype = dtype;
+    m.rows = rows;
+    m.cols = cols;
+    m.ld = ld;
+    m.win.pfa = 0.5;
+    plain_geometry(&m, d);
+    d.m.x = x;
+    d.m.dtype = dtype;
+    d.m.rows = (int32_t)rows;
+    d.m.cols = (int32_t)cols;
+    d.m.ld = ld;
+    d.S = sat;
+    d.left = (double *)ws;
+    d.V = (double *)((char *)ws + align_up((size_t)(d.n_strips * rows) * 8, 256));
+    a.n_maps = 1;
+    a.sat_units = (uint32_t)plain_sat_units(d);
+    a.carry_blocks = (uint32_t)plain_carry_blocks(&m);
+    const hipError_t e = launch_plain(a, 0, false, false, stream);
+    return e == hipSuccess ? CFAR_OK : hip_error(e, "launch(plain sat2d)");
 }
 
 // ---------------------------------------------------------------------------
@@ -810,7 +1019,8 @@ size_t sat2d_bytes(int64_t rows, int64_t cols, int32_t form)
 size_t sat2d_workspace_bytes(int64_t rows, int64_t cols, int32_t form)
 {
     if (rows < 1 || cols < 1 || rows > kMaxDim || cols > kMaxDim) return 0;
-    if (form != CFAR_FORM_PLAIN && form != CFAR_FORM_TILED) return 0;
+    if (form == CFAR_FORM_PLAIN) return plain_sat_ws_bytes(rows, cols);
+    if (form != CFAR_FORM_TILED) return 0;
     return sat_ws_bytes(rows, cols);
 }
 
@@ -825,8 +1035,14 @@ int sat2d(const void *x, int32_t dtype, int64_t rows, int64_t cols, int64_t ld, 
     if (!x || !sat_out || !ws) return set_error(CFAR_EINVAL, "NULL pointer argument");
     const size_t need = sat2d_bytes(rows, cols, form);
     if (sat_bytes < need) return set_error(CFAR_ENOSPC, "sat_bytes %zu < %zu needed", sat_bytes, need);
-    const size_t wneed = sat_ws_bytes(rows, cols);
+    const size_t wneed = form == CFAR_FORM_PLAIN ? plain_sat_ws_bytes(rows, cols) : sat_ws_bytes(rows, cols);
     if (ws_bytes < wneed) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, wneed);
+    if (form == CFAR_FORM_PLAIN) {
+        if (rows * ((cols + kPlainW - 1) / kPlainW) >= ((int64_t)1 << 31) ||
+            ((rows + plain_chunk() - 1) / plain_chunk()) * ((cols + kPlainW - 1) / kPlainW) >= ((int64_t)1 << 31))
+            return set_error(CFAR_EINVAL, "map too large for sat2d");
+        return run_plain_sat2d(x, dtype, rows, cols, ld, (double *)sat_out, ws, (hipStream_t)stream);
+    }
     SatWs sw = sat_ws_layout(ws, rows, cols);
     hipError_t e = launch_sat2d(x, dtype, rows, cols, ld, form, sat_out, sw, (hipStream_t)stream);
     if (e != hipSuccess) return hip_error(e, "launch(sat2d)");
@@ -838,10 +1054,10 @@ size_t cfar_workspace_bytes(const cfar_map *maps, int32_t n, int32_t form)
     if (!maps || n < 1) { set_error(CFAR_EINVAL, "maps is NULL or n < 1"); return 0; }
     for (int i = 0; i < n; ++i)
         if (validate_map(&maps[i], i, form) != CFAR_OK) return 0;
-    if (form == CFAR_FORM_PLAIN || form == CFAR_FORM_DIRECT) {
+    if (form == CFAR_FORM_PLAIN) return plain_ws_bytes(maps, n);
+    if (form == CFAR_FORM_DIRECT) {
         size_t need = 0;
-        for (int i = 0; i < n; ++i)
-            need = std::max(need, form == CFAR_FORM_PLAIN ? plain_single_ws(&maps[i]) : lut_bytes(&maps[i]));
+        for (int i = 0; i < n; ++i) need = std::max(need, lut_bytes(&maps[i]));
         return need;
     }
     uint64_t total_units = 0;
@@ -859,7 +1075,7 @@ int cfar2d(const cfar_map *m, int32_t form, void *ws, size_t ws_bytes, void *str
 {
     int rc = validate_map(m, 0, form);
     if (rc != CFAR_OK) return rc;
-    if (form == CFAR_FORM_PLAIN) return run_plain_single(m, ws, ws_bytes, (hipStream_t)stream);
+    if (form == CFAR_FORM_PLAIN) return run_plain_batch(m, 1, ws, ws_bytes, (hipStream_t)stream);
     if (form == CFAR_FORM_DIRECT) return run_direct_single(m, ws, ws_bytes, (hipStream_t)stream);
     return run_tiled_single(m, choose_plan(m), ws, ws_bytes, (hipStream_t)stream);
 }
@@ -882,16 +1098,7 @@ int cfar2d_batched(const cfar_map *maps, int32_t n, int32_t form, int32_t flags,
         if (rc != CFAR_OK) return rc;
     }
     hipStream_t s = (hipStream_t)stream;
-    if (form == CFAR_FORM_PLAIN) {
-        size_t need = 0;
-        for (int i = 0; i < n; ++i) need = std::max(need, plain_single_ws(&maps[i]));
-        if (ws_bytes < need) return set_error(CFAR_ENOSPC, "ws_bytes %zu < %zu needed", ws_bytes, need);
-        for (int i = 0; i < n; ++i) {
-            int rc = run_plain_single(&maps[i], ws, ws_bytes, s);
-            if (rc != CFAR_OK) return rc;
-        }
-        return CFAR_OK;
-    }
+    if (form == CFAR_FORM_PLAIN) return run_plain_batch(maps, n, ws, ws_bytes, s);
     if (form == CFAR_FORM_DIRECT) {  // one table + one stencil launch per map, in order on the stream
         size_t need = 0;
         for (int i = 0; i < n; ++i) need = std::max(need, lut_bytes(&maps[i]));

@@ -54,6 +54,40 @@ struct FusedArgs {
     MapDesc single;
 };
 
+// One map of the PLAIN form (integral image in FP64, then the stencil).
+struct PlainDesc {
+    MapDesc m;            // map, mask, optional outputs, threshold table, window
+    double *S;            // rows x cols integral image, leading dimension cols
+    double *left;         // [n_strips][rows]: row totals per strip, then the sums left of each strip
+    double *V;            // [n_chunks][cols]: strip prefix of chunk column totals, then the sums above
+    int32_t n_strips;     // integral image: strips of kPlainW columns
+    int32_t n_chunks;     // integral image: chunks of `chunk` rows
+    int32_t chunk;
+    int32_t st_k;         // stencil: columns per lane (4 or 8; 0: the map takes the per-cell stencil)
+    int32_t st_halo;      // stencil: column halo, >= hf + 1, multiple of max(4, st_k)
+    int32_t st_tw;        // stencil: output columns per strip = 64*st_k - 2*st_halo
+    int32_t st_strips;    // stencil strips
+    int32_t st_band;      // stencil: output rows per work unit
+    int32_t st_bands;     // stencil bands
+    int32_t st_xcd;       // stencil: strips per XCD group (0: units in plain band-major order)
+    int32_t pad[16];
+};
+static_assert(sizeof(PlainDesc) == 256, "PlainDesc must stay 256 bytes");
+
+constexpr int kPlainK = 4;              // integral image: columns per lane
+constexpr int kPlainW = 64 * kPlainK;   // integral image: strip width
+
+// Arguments of the PLAIN kernels.  descs == nullptr: the one map in `single`.
+struct PlainArgs {
+    const PlainDesc *descs;     // n_maps descriptors (device), or nullptr
+    const uint32_t *sat_base;   // [n_maps + 1] first integral-image unit of every map (device)
+    const uint32_t *st_base;    // [n_maps + 1] first stencil unit of every map (device)
+    const uint32_t *blk_base;   // [n_maps + 1] first carry workgroup of every map (device)
+    uint32_t n_maps;
+    uint32_t sat_units, st_units, carry_blocks;
+    PlainDesc single;
+};
+
 // Layout of the TILED batch workspace.  The host writes the first part
 // (header + descriptors + unit tables) with one host-to-device copy; the
 // threshold tables that follow are filled on the device.
@@ -108,13 +142,20 @@ size_t tiled_single_ws_bytes(const cfar_map *m);
 hipError_t launch_sat2d(const void *x, int dtype, int64_t rows, int64_t cols, int64_t ld,
                         int out_form, void *sat, const SatWs &ws, hipStream_t stream);
 
-// Threshold tables (and the work counter) for `n` maps.  descs: device
-// descriptor table, or nullptr with `single` used instead.
-hipError_t launch_lut(const MapDesc *descs, const MapDesc &single, int n, uint32_t *counter,
+// Threshold tables (and the work counters) for `n` maps.  descs: device
+// table of descriptors that start with a MapDesc, `stride` bytes apart, or
+// nullptr with `single` used instead.
+hipError_t launch_lut(const void *descs, size_t stride, const MapDesc &single, int n, uint32_t *counter,
                       hipStream_t stream);
 
 // Eight-corner stencil over the PLAIN FP64 SAT of one map.
 hipError_t launch_stencil_plain(const MapDesc &d, const double *sat, hipStream_t stream);
+
+// PLAIN form (plain.hip): integral image (aggregate, carry, finalize) and
+// the stencil, each one launch over the units of every map in `a`.
+// with_stencil = false stops after the integral image (sat2d).  Maps whose
+// st_k is 0 get no stencil units (the caller runs launch_stencil_plain).
+hipError_t launch_plain(const PlainArgs &a, int dtype_mask, bool with_stencil, bool any_out, hipStream_t stream);
 
 // DIRECT form: output tile of one workgroup (rows x columns) and its LDS.
 constexpr int kDirTH = 4, kDirTW = 64;

@@ -277,11 +277,11 @@ hipError_t launch_sat2d(const void *x, int dtype, int64_t rows, int64_t cols, in
 // ---------------------------------------------------------------------------
 // Threshold tables (eq. 2): lut[n] = expm1(-ln(Pfa)/n) = alpha(n) / n.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) lut_kernel(const MapDesc *__restrict__ descs, MapDesc single,
+__global__ void __launch_bounds__(256) lut_kernel(const char *__restrict__ descs, uint32_t stride, MapDesc single,
                                                   uint32_t *counter)
 {
     if (blockIdx.x == 0 && threadIdx.x < 16 && counter) counter[threadIdx.x] = 0u;
-    const MapDesc *d = descs ? descs + blockIdx.x : &single;
+    const MapDesc *d = descs ? (const MapDesc *)(descs + (size_t)blockIdx.x * stride) : &single;
     double *lut = d->lut;
     const double nl = d->neg_log_pfa;
     const int n_full = d->n_full;
@@ -289,9 +289,11 @@ __global__ void __launch_bounds__(256) lut_kernel(const MapDesc *__restrict__ de
         lut[n] = n == 0 ? __builtin_nan("") : expm1(nl / (double)n);
 }
 
-hipError_t launch_lut(const MapDesc *descs, const MapDesc &single, int n, uint32_t *counter, hipStream_t stream)
+hipError_t launch_lut(const void *descs, size_t stride, const MapDesc &single, int n, uint32_t *counter,
+                      hipStream_t stream)
 {
-    hipLaunchKernelGGL(lut_kernel, dim3((unsigned)(descs ? n : 1)), dim3(256), 0, stream, descs, single, counter);
+    hipLaunchKernelGGL(lut_kernel, dim3((unsigned)(descs ? n : 1)), dim3(256), 0, stream, (const char *)descs,
+                       (uint32_t)stride, single, counter);
     return hipGetLastError();
 }
 

@@ -102,3 +102,28 @@ def sample_cells(R, F, h_r, h_f, targets=None, n_random=20000, seed=0):
                         rows.append(np.array([a]))
                         cols.append(np.array([b]))
     return np.concatenate(rows).astype(np.int64), np.concatenate(cols).astype(np.int64)
+
+
+def decode_tiled_sat(buf, rows, cols):
+    """S(i,j) from the bytes of sat2d's TILED layout (as its declaration in
+    include/cfar2d.h describes it), in FP64 on the host: FP32 local sums of
+    32 x 32 tiles, FP64 row lines every 32 rows and FP64 column lines every
+    32 columns, each region starting at a 256-byte boundary."""
+    line = 32
+
+    def up(v):
+        return (v + 255) // 256 * 256
+
+    raw = np.ascontiguousarray(buf).view(np.uint8)
+    n_i, n_j = (rows + line - 1) // line, (cols + line - 1) // line
+    loc_b, row_b = up(rows * cols * 4), up(n_i * cols * 8)
+    loc = raw[:rows * cols * 4].view(np.float32).reshape(rows, cols).astype(np.float64)
+    rowline = raw[loc_b:loc_b + n_i * cols * 8].view(np.float64).reshape(n_i, cols)
+    colline = raw[loc_b + row_b:loc_b + row_b + n_j * rows * 8].view(np.float64).reshape(n_j, rows)
+    ti = np.arange(rows) // line
+    tj = np.arange(cols) // line
+    top = rowline[ti, :]                           # S(32 I - 1, j)
+    left = colline[tj, :].T                        # S(i, 32 J - 1)
+    cj = np.maximum(tj * line - 1, 0)
+    corner = rowline[ti][:, cj] * (tj > 0)[None, :]  # S(32 I - 1, 32 J - 1)
+    return top + left - corner + loc

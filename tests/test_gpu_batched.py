@@ -111,3 +111,28 @@ def test_graph_replays_match_eager():
     for k in range(len(xs)):
         assert np.array_equal(masks[k].cpu().numpy(), ref[k][0])
         np.testing.assert_array_equal(sts[k].cpu().numpy(), 2.0 * ref[k][1])
+
+
+def test_plain_batch_mixed_stencils():
+    """One PLAIN batch whose maps take every stencil path: 256-column strips
+    (hf <= 60), 512-column strips (61..247) and the per-cell stencil (wider),
+    FP32 and FP64 maps, some with the optional outputs; each map against the
+    oracle on every cell."""
+    wins = [(1, 1, 4, 4, 1e-3), (2, 30, 3, 40, 1e-4), (1, 3, 2, 280, 1e-3), (3, 2, 9, 58, 1e-5),
+            (0, 0, 2, 2, 0.5), (4, 4, 24, 24, 1e-6)]
+    shapes = [(70, 300), (33, 1500), (41, 900), (200, 129), (1, 1), (257, 513)]
+    specs = []
+    for k, ((R, F), w) in enumerate(zip(shapes, wins)):
+        specs.append(synth.MapSpec(R, F, "f32" if k % 2 == 0 else "f64", "exp", 2.0, n_targets=2,
+                                   guard_r=w[0], guard_f=w[1], train_r=w[2], train_f=w[3], pfa=w[4],
+                                   seed=(9, k)))
+    xs_np = [synth.generate(s) for s in specs]
+    xs = [torch.from_numpy(x).to(DEV) for x in xs_np]
+    masks, sts = _alloc(xs)
+    outs = [sts[k] if k % 3 == 0 else None for k in range(len(xs))]
+    say("plain mixed batch", [(s.rows, s.cols, s.window) for s in specs])
+    C.cfar2d_batched(xs, [s.window for s in specs], C.PLAIN, masks=masks, train_sums=outs, flags=0)
+    torch.cuda.synchronize()
+    for k, s in enumerate(specs):
+        check_full(xs_np[k], s.window, masks[k].cpu().numpy(),
+                   sts[k].cpu().numpy() if outs[k] is not None else None, None, "plain")

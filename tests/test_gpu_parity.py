@@ -12,7 +12,7 @@ import torch
 import oracle
 from paper_2012_11077_amd import cfar2d as C
 from paper_2012_11077_amd import synth
-from parity import check_cells, check_full, sample_cells, say
+from parity import check_cells, check_full, decode_tiled_sat, sample_cells, say
 
 pytestmark = pytest.mark.gpu
 
@@ -132,7 +132,7 @@ def test_sat2d_tiled_layout():
         say("sat2d tiled", R, F)
         buf = C.sat2d(torch.from_numpy(x).to(DEV), C.TILED)
         torch.cuda.synchronize()
-        S = C.decode_tiled_sat(buf, R, F).cpu().numpy()
+        S = decode_tiled_sat(buf.cpu().numpy(), R, F)
         ref = oracle.sat(x)[1:, 1:]
         # FP32 local sums hold at most 32 x 32 cells: error within a few
         # FP32 ulps of the local sum, far below the SAT entries themselves
@@ -141,7 +141,7 @@ def test_sat2d_tiled_layout():
     xi = rng.integers(0, 64, size=(97, 131)).astype(np.float32)
     buf = C.sat2d(torch.from_numpy(xi).to(DEV), C.TILED)
     torch.cuda.synchronize()
-    assert np.array_equal(C.decode_tiled_sat(buf, 97, 131).cpu().numpy(), oracle.sat(xi)[1:, 1:])
+    assert np.array_equal(decode_tiled_sat(buf.cpu().numpy(), 97, 131), oracle.sat(xi)[1:, 1:])
 
 
 def test_repeat_is_bitwise_deterministic():
@@ -224,3 +224,14 @@ def test_padded_rows_and_right_aligned_last_strip(cols):
             torch.cuda.synchronize()
             check_full(x_np, spec.window, mv.cpu().numpy(), None, None, "tiled", ref=ref)
             assert (mbig[:, cols:].cpu().numpy() == 7).all()
+
+
+def test_plain_window_wider_than_strips():
+    """PLAIN form with a column half-width above what a 512-column strip
+    holds (the per-cell stencil), on one map: every cell against the oracle."""
+    spec = synth.MapSpec(37, 1200, "f64", "exp", 2.0, n_targets=2, guard_r=1, guard_f=2, train_r=3,
+                         train_f=300, pfa=1e-3, seed=(41,))
+    x = synth.generate(spec)
+    say("plain wide window", spec.rows, spec.cols, spec.window)
+    mask, st, th = _run(x, spec.window, "plain")
+    check_full(x, spec.window, mask, st, th, "plain")
