@@ -214,7 +214,56 @@ def precision_report():
             st = out[name]["st"]
             rel = np.where(st_o != 0, np.abs(st - st_o) / np.abs(st_o), 0.0)
             rep[key + "_max_rel_box_sum_err"] = float(rel.max())
+    # the FP32-tile-local integral image with FP64 carries (sat2d's TILED
+    # layout): training sums from its corners, against the oracle's
+    buf = C.sat2d(x, C.TILED).cpu().numpy()
+    torch.cuda.synchronize()
+    rep["fp32_local_sat_max_rel_box_sum_err"] = fp32_local_box_err(buf, spec.rows, spec.cols, spec.window, st_o)
     return rep
+
+
+def fp32_local_box_err(buf, rows, cols, window, st_o, block=1024):
+    """Largest relative error of the training sums (eq. 4, clipped windows)
+    taken from the corners of sat2d's TILED layout (FP32 sums inside 32 x 32
+    tiles, FP64 row and column lines every 32 rows / columns; decoded in FP64
+    here) against the oracle's training sums st_o."""
+    line = 32
+
+    def up(v):
+        return (v + 255) // 256 * 256
+
+    raw = np.ascontiguousarray(buf).view(np.uint8)
+    n_i, n_j = (rows + line - 1) // line, (cols + line - 1) // line
+    loc_b, row_b = up(rows * cols * 4), up(n_i * cols * 8)
+    loc = raw[:rows * cols * 4].view(np.float32).reshape(rows, cols)
+    rowline = raw[loc_b:loc_b + n_i * cols * 8].view(np.float64).reshape(n_i, cols)
+    colline = raw[loc_b + row_b:loc_b + row_b + n_j * rows * 8].view(np.float64).reshape(n_j, rows)
+    tj = np.arange(cols) // line
+    cj = np.maximum(tj * line - 1, 0)
+    # S with a zero row and column in front: P[i+1, j+1] = S(i, j)
+    P = np.zeros((rows + 1, cols + 1))
+    for i0 in range(0, rows, block):
+        i1 = min(i0 + block, rows)
+        ti = np.arange(i0, i1) // line
+        P[i0 + 1:i1 + 1, 1:] = (rowline[ti, :] + colline[tj, i0:i1].T - rowline[ti][:, cj] * (tj > 0)[None, :]
+                                + loc[i0:i1].astype(np.float64))
+    gr, gf, tr, tf, _ = window
+    hr, hf = gr + tr, gf + tf
+    jj = np.arange(cols)
+    co0, co1 = np.maximum(jj - hf, 0), np.minimum(jj + hf, cols - 1) + 1
+    ci0, ci1 = np.maximum(jj - gf, 0), np.minimum(jj + gf, cols - 1) + 1
+    worst = 0.0
+    for i0 in range(0, rows, block):
+        ii = np.arange(i0, min(i0 + block, rows))
+        ro0, ro1 = np.maximum(ii - hr, 0), np.minimum(ii + hr, rows - 1) + 1
+        ri0, ri1 = np.maximum(ii - gr, 0), np.minimum(ii + gr, rows - 1) + 1
+        outer = P[ro1][:, co1] - P[ro0][:, co1] - P[ro1][:, co0] + P[ro0][:, co0]
+        inner = P[ri1][:, ci1] - P[ri0][:, ci1] - P[ri1][:, ci0] + P[ri0][:, ci0]
+        ref = st_o[ii]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            rel = np.where(ref != 0, np.abs((outer - inner) - ref) / np.abs(ref), 0.0)
+        worst = max(worst, float(rel.max()))
+    return worst
 
 
 # Table I of the paper (workstation, Intel Core i5-6200U): CA-CFAR without and

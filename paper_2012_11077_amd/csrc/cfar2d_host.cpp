@@ -168,12 +168,39 @@ struct PlanRule {
 static std::mutex g_plan_mu;
 static std::vector<PlanRule> g_rules;
 
-// Built-in cost model (fitted to timings of one wave per strip row on
-// gfx950): a strip row costs c(k) with c(2) = 0.5, c(4) = 1, c(8) = 3
-// (c(2) = 0.45 when k = 2 can hold every window row in its LDS ring and k = 4
+// Built-in cost model (fitted to timings of the uneven batch on gfx950): a
+// strip row costs c(k) with c(2) = c(4) = 1 (the row step's scans, LDS
+// exchange and loop work are per wave, whatever the strip width), c(8) = 3
+// (c(2) = 0.9 when k = 2 can hold its guard rows in the LDS ring and k = 4
 // cannot); a map narrower than one strip whose last column falls inside a
-// lane takes the general path, about three times the cost.  64 rows per unit
-// keeps the persistent launch's tail short.
+// lane takes the general path, about three times the cost.  Rows per unit:
+// 256 for maps of at least 1024 rows, 64 below (CFAR2D_RS_TALL,
+// CFAR2D_RS_SHORT and CFAR2D_COST_K2 override them, for tuning).
+static int env_int(const char *name, int dflt)
+{
+    const char *e = std::getenv(name);
+    return e && std::atoi(e) > 0 ? std::atoi(e) : dflt;
+}
+static int rs_tall()
+{
+    static const int v = env_int("CFAR2D_RS_TALL", 256);
+    return v;
+}
+static int rs_short()
+{
+    static const int v = env_int("CFAR2D_RS_SHORT", 64);
+    return v;
+}
+static double cost_k2()
+{
+    static double v = -1.0;
+    if (v < 0.0) {
+        const char *e = std::getenv("CFAR2D_COST_K2");
+        v = e && std::atof(e) > 0.0 ? std::atof(e) : 1.0;
+    }
+    return v;
+}
+
 static cfar_plan default_plan(const cfar_map *m)
 {
     const int hr = m->win.guard_r + m->win.train_r;
@@ -186,7 +213,7 @@ static cfar_plan default_plan(const cfar_map *m)
         if (!plan_geometry(m, k, 64, &p)) continue;
         const bool ring2 = 2 * hr + 2 <= ring_rows_cap(2, m->dtype, ring_budget());
         const bool ring4 = 2 * hr + 2 <= ring_rows_cap(4, m->dtype, ring_budget());
-        const double c = k == 2 ? (ring2 && !ring4 ? 0.45 : 0.5) : k == 4 ? 1.0 : 3.0;
+        const double c = k == 2 ? (ring2 && !ring4 ? 0.9 : 1.0) * cost_k2() : k == 4 ? 1.0 : 3.0;
         double cost = (double)p.n_strips * c;
         // a map narrower than one strip whose last column falls inside a
         // lane takes the general path
@@ -198,7 +225,7 @@ static cfar_plan default_plan(const cfar_map *m)
     // tall maps: longer units spread the warm-up rows (2 hr + 1 per unit)
     // over more output rows; the rest keep short units, which also keep the
     // end of a batched launch short (its maps run largest first)
-    out.rows_per_unit = (int)std::min<int64_t>(m->rows >= 1024 ? 128 : 64, m->rows);
+    out.rows_per_unit = (int)std::min<int64_t>(m->rows >= 1024 ? rs_tall() : rs_short(), m->rows);
     // a map of few units runs on few waves, each walking its rows in turn:
     // shorter units (not below 16 rows) spread it over more of the chip
     Plan g;
@@ -291,25 +318,19 @@ constexpr int kPlainBand = 16;
 
 // Rows per unit of the PLAIN form's kernels (CFAR2D_PLAIN_CHUNK and
 // CFAR2D_PLAIN_BAND override the defaults, for tuning).
-static int env_or(const char *name, int dflt)
-{
-    const char *e = std::getenv(name);
-    const int v = e ? std::atoi(e) : 0;
-    return v > 0 ? v : dflt;
-}
 static int plain_chunk()
 {
-    static const int v = env_or("CFAR2D_PLAIN_CHUNK", kPlainChunk);
+    static const int v = env_int("CFAR2D_PLAIN_CHUNK", kPlainChunk);
     return v;
 }
 static int plain_band()
 {
-    static const int v = env_or("CFAR2D_PLAIN_BAND", kPlainBand);
+    static const int v = env_int("CFAR2D_PLAIN_BAND", kPlainBand);
     return v;
 }
 static int plain_xcd()
 {
-    static const int v = env_or("CFAR2D_PLAIN_XCD", 2) - 1;  // 1 (default): XCD-grouped stencil units
+    static const int v = env_int("CFAR2D_PLAIN_XCD", 2) - 1;  // 1 (default): XCD-grouped stencil units
     return v;
 }
 
