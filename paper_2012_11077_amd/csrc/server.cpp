@@ -146,6 +146,10 @@ struct cfar_server {
     // failure path can be tested without a device fault
     bool fail_tag_set = false;
     uint64_t fail_tag = 0;
+    // CFAR2D_SERVER_GRAPH=1 (read at creation): batches launch with
+    // CFAR_BATCH_GRAPH (a replay where a stream's previous batch had the same
+    // layout, else a capture)
+    int batch_flags = 0;
     std::thread thr;
 };
 
@@ -234,8 +238,8 @@ int launch(cfar_server *s, Batch &b)
         }
         maps.push_back(m);
     }
-    int rc = cfar2d_batched(maps.data(), (int32_t)maps.size(), CFAR_FORM_TILED, 0, s->pool_base + ws.off, ws.bytes,
-                            st);
+    int rc = cfar2d_batched(maps.data(), (int32_t)maps.size(), CFAR_FORM_TILED, s->batch_flags, s->pool_base + ws.off,
+                            ws.bytes, st);
     if (rc != CFAR_OK) return rc;
     for (size_t i = 0; i < b.frames.size(); ++i) {
         const Frame &f = b.frames[i];
@@ -468,6 +472,8 @@ int cfar_server_create(const cfar_server_opts *opts, cfar_server **out)
         s->fail_tag_set = true;
         s->fail_tag = std::strtoull(ft, nullptr, 10);
     }
+    if (const char *g = std::getenv("CFAR2D_SERVER_GRAPH"))
+        if (std::atoi(g) == 1) s->batch_flags = CFAR_BATCH_GRAPH;
     e = hipMalloc((void **)&s->pool_base, o.device_budget_bytes);
     if (e != hipSuccess) return hip_error(e, "hipMalloc(server pool)");
     s->pool_bytes = o.device_budget_bytes;
