@@ -44,6 +44,11 @@
 #ifndef CFAR_PLAIN_PD
 #define CFAR_PLAIN_PD 2
 #endif
+// Interior rows of the stencil in chains of step hr - gr (two image rows
+// loaded per row instead of four).
+#ifndef CFAR_PLAIN_CHAIN
+#define CFAR_PLAIN_CHAIN 1
+#endif
 
 namespace cfar {
 
@@ -589,12 +594,64 @@ struct StUnit {
         }
     }
 
+    // Rows [r0, r1) whose windows lie inside the map, in chains of step
+    // d = hr - gr: row i + d takes as its guard window's corner rows the
+    // outer window's of row i (i+d+gr = i+hr, i+d-hr-1 = i-gr-1), so only
+    // two integral-image rows are loaded per row after a chain's first.
+    // Rows r0, r0+d, r0+2d, ..., then r0+1, r0+1+d, ...; each step issues
+    // the next row's loads before its own work.
+    __device__ __forceinline__ void load_chain(int i, Rows &w) const
+    {
+        ld_row<K, double>(srow(i + hr), voff_s, w.a);
+        ld_row<K, double>(srow(i - gr - 1), voff_s, w.e);
+        ld_row<K, T>(xrow(i), voff_x, w.u);
+    }
+    __device__ __forceinline__ void interior_chains(int r0, int r1, int dd)
+    {
+        Rows w[2];
+        load(r0, w[0]);
+        int i = r0, t = 0;
+        auto step = [&](Rows &cur, Rows &nxt) -> bool {
+            const int j = i + dd;
+            const bool cont = j < r1;  // wave-uniform: the chain goes on
+            const bool more = cont || (t + 1 < dd && r0 + t + 1 < r1);
+            if (cont) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    nxt.c[k] = cur.a[k];
+                    nxt.b[k] = cur.e[k];
+                }
+                load_chain(j, nxt);
+            } else if (more) {
+                load(r0 + t + 1, nxt);
+            }
+            double po[K], pi[K];
+            T u[K];
+            diff(cur, po, pi, u);
+            finish(i, po, pi, u, beta_col);
+            if (!cont) {
+                ++t;
+                i = r0 + t;
+            } else {
+                i = j;
+            }
+            return more;
+        };
+        for (;;) {
+            if (!step(w[0], w[1])) break;
+            if (!step(w[1], w[0])) break;
+        }
+    }
+
     __device__ __forceinline__ void run()
     {
         const int i0 = min(max(hr, ra), rb);  // first row whose windows the map does not clip
         const int i1 = max(min(R - hr, rb), i0);
         border_rows(ra, i0);
-        interior_rows(i0, i1);
+        if (CFAR_PLAIN_CHAIN && hr > gr && i1 - i0 > hr - gr)  // wave-uniform
+            interior_chains(i0, i1, hr - gr);
+        else
+            interior_rows(i0, i1);
         border_rows(i1, rb);
     }
 };
