@@ -90,7 +90,7 @@ struct Unit {
     uint32_t voff;          // lane byte offset into a map row (kOff: left of column 0)
     uint32_t moff;          // lane byte offset of its K mask bytes (kOff: no full ownership)
     uint32_t poff;          // lane byte offset of a partly owned lane (kOff: none)
-    bool part;              // some lane owns only part of its K columns (wave-uniform)
+    uint64_t part;          // lanes that own only part of their K columns (a wave-wide ballot)
     double beta_col[K];     // beta on rows without row clipping
     Corner<K> c_oh, c_ol, c_ih, c_il;
     double Co[K], Ci[K];
@@ -123,7 +123,7 @@ struct Unit {
         const bool full = own && c_lane + K <= c_out1;
         moff = full ? (uint32_t)c_lane : kOff;
         poff = own && !full ? (uint32_t)c_lane : kOff;
-        part = __builtin_amdgcn_ballot_w64(own && !full) != 0ull;
+        part = __builtin_amdgcn_ballot_w64(own && !full);
         const CFAR_GLOBAL double *lut = (const CFAR_GLOBAL double *)d.lut;
 #pragma unroll
         for (int k = 0; k < K; ++k) beta_col[k] = lut[nt_of(2 * hr + 1, 2 * gr + 1, k)];
@@ -222,23 +222,22 @@ struct Unit {
         ld_row<K, T>(xrow(r), voff, s.u);
     }
 
-    // Running column sums for row r (rows outside the map weigh zero: they
-    // were never added), then the strip prefix of both into LDS.  (One
-    // buffer per window: a wave's LDS operations complete in order, so the
-    // corner reads of a row are done before the next row's writes.)
-    __device__ __forceinline__ void accumulate_publish(int r, const T (&a)[K], const Rest &s)
+    // Running column sums for row r, then the strip prefix of both into LDS.
+    // Rows outside the map read as zeros, so adding and taking them off
+    // leaves the sums as they are.  (One buffer per window: a wave's LDS
+    // operations complete in order, so the corner reads of a row are done
+    // before the next row's writes.)
+    __device__ __forceinline__ void accumulate_publish(const T (&a)[K], const Rest &s)
     {
-        accumulate_publish(r, a, s.b, s.c, s.e);
+        accumulate_publish(a, s.b, s.c, s.e);
     }
-    __device__ __forceinline__ void accumulate_publish(int r, const T (&a)[K], const T (&b)[K], const T (&c)[K],
+    __device__ __forceinline__ void accumulate_publish(const T (&a)[K], const T (&b)[K], const T (&c)[K],
                                                        const T (&e)[K])
     {
-        const double wa = in_map(r + hr, R), wb = in_map(r + gr, R);
-        const double wc = -in_map(r - gr - 1, R), we = -in_map(r - hr - 1, R);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            Co[k] = __builtin_fma(we, (double)e[k], __builtin_fma(wa, (double)a[k], Co[k]));
-            Ci[k] = __builtin_fma(wc, (double)c[k], __builtin_fma(wb, (double)b[k], Ci[k]));
+            Co[k] = (Co[k] + (double)a[k]) - (double)e[k];
+            Ci[k] = (Ci[k] + (double)b[k]) - (double)c[k];
         }
         double po[K], pi[K];
         po[0] = Co[0];
@@ -283,6 +282,11 @@ struct Unit {
     // and the stores.
     __device__ __forceinline__ void decide(int r, const Corners &c, const T (&u)[K], const double (&beta)[K])
     {
+        decide(r, c, u, beta, mrow(r));
+    }
+    __device__ __forceinline__ void decide(int r, const Corners &c, const T (&u)[K], const double (&beta)[K],
+                                           __amdgpu_buffer_rsrc_t mrs)
+    {
         typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
         uint32_t bits[(K + 3) / 4];
 #pragma unroll
@@ -294,7 +298,6 @@ struct Unit {
             thr[k] = beta[k] * st[k];  // NaN where N_T = 0 (table entry 0): no detection
             bits[k / 4] |= ((double)u[k] > thr[k]) ? (1u << (8 * (k % 4))) : 0u;
         }
-        const __amdgpu_buffer_rsrc_t mrs = mrow(r);
         const uint32_t ms = 0u;
         if constexpr (K == 2) {
             __builtin_amdgcn_raw_buffer_store_b16((uint16_t)bits[0], mrs, moff, ms, 0);
@@ -304,7 +307,9 @@ struct Unit {
             const u32x2 w = {bits[0], bits[1]};
             __builtin_amdgcn_raw_buffer_store_b64(w, mrs, moff, ms, 0);
         }
-        if (part) {  // wave-uniform: the lane that straddles the map's last column stores bytes
+        uint64_t pf = part;
+        asm volatile("" : "+s"(pf));  // a scalar branch, not a lane mask
+        if (pf != 0ull) {  // wave-uniform: the lane that straddles the map's last column stores bytes
 #pragma unroll
             for (int k = 0; k < K; ++k)
                 __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(bits[k / 4] >> (8 * (k % 4))), mrs,
@@ -366,7 +371,7 @@ struct Unit {
             double beta[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) beta[k] = lut[nt_of(nro, nri, k)];
-            accumulate_publish(r, a, s);
+            accumulate_publish(a, s);
             Corners c;
             corners(c);
             decide(r, c, s.u, beta);
@@ -380,7 +385,7 @@ struct Unit {
     __device__ __forceinline__ void irow(int r, int r1, T (&lead)[PL][K], Rest (&rest)[PD])
     {
         constexpr int JL = J % PL, JR = J % PD;
-        accumulate_publish(r, lead[JL], rest[JR]);
+        accumulate_publish(lead[JL], rest[JR]);
         T u[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) u[k] = rest[JR].u[k];
@@ -464,12 +469,49 @@ struct Unit {
         sb = sb + 1 == D ? 0 : sb + 1;
         su = su + 1 == D ? 0 : su + 1;
         sc = sc + 1 == D ? 0 : sc + 1;
-        accumulate_publish(r, lead[JL], rest[JR].b, c, rest[JR].e);
+        accumulate_publish(lead[JL], rest[JR].b, c, rest[JR].e);
         load_lead(min(r + PL, r1 - 1), lead[JL]);
         load_rest(min(r + PDR, r1 - 1), rest[JR]);
         Corners cr;
         corners(cr);
         decide(r, cr, u, beta_col);
+    }
+    // Byte addresses of the rows the next fast step loads (lead row, rows
+    // r+gr and r-hr-1) and of its mask row; each step moves all four down a
+    // row.
+    struct Rows {
+        uint64_t l, b, e, m;
+    };
+    // One row of the ring loop where no load needs clamping (every row it
+    // loads lies in the unit's rows and in the map): the row resources come
+    // from addresses that move by a row per step instead of being rebuilt
+    // from the row index.
+    template <int J>
+    __device__ __forceinline__ void irow_ring_fast(int r, T (&lead)[PL][K], RestR (&rest)[PDR], int &sb, int &su,
+                                                   int &sc, Rows &w)
+    {
+        constexpr int JL = J % PL, JR = J % PDR;
+        T u[K], c[K];
+        ring_put(sb, rest[JR].b);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ring_get(su, u);
+        ring_get(sc, c);
+        sb = sb + 1 == D ? 0 : sb + 1;
+        su = su + 1 == D ? 0 : su + 1;
+        sc = sc + 1 == D ? 0 : sc + 1;
+        accumulate_publish(lead[JL], rest[JR].b, c, rest[JR].e);
+        ld_row<K, T>(rsrc(w.l, xbytes), voff, lead[JL]);
+        ld_row<K, T>(rsrc(w.b, xbytes), voff, rest[JR].b);
+        ld_row<K, T>(rsrc(w.e, xbytes), voff, rest[JR].e);
+        w.l += p32;
+        w.b += p32;
+        w.e += p32;
+        Corners cr;
+        corners(cr);
+        decide(r, cr, u, beta_col, rsrc(w.m, (uint32_t)F));
+        w.m += mp32;
     }
     // Rows r0-gr-1 .. r0+gr-1 into the guard ring, four loads in flight.
     __device__ __forceinline__ void fill_ring(int r0)
@@ -497,6 +539,19 @@ struct Unit {
         for (int j = 0; j < PDR; ++j) load_rest(min(r0 + j, r1 - 1), rest[j]);
         int sb = (r0 + gr) % D, su = r0 % D, sc = (r0 - gr - 1 + D) % D;
         int r = r0;
+        // Steps whose loads (up to PL and PDR rows ahead) stay below r1 need
+        // no clamping: rows r+hr+PL <= r1-1+hr and r-hr-1+PDR >= 0 (r >= hr)
+        // lie in the unit's rows and in the map.
+        constexpr int PM = PL > PDR ? PL : PDR;
+        if (r + UR + PM <= r1) {
+            Rows w;
+            w.l = xlo + (uint64_t)((uint32_t)(r + PL + hr - lo) * p32);
+            w.b = xlo + (uint64_t)((uint32_t)(r + PDR + gr - lo) * p32);
+            w.e = xlo + (uint64_t)((uint32_t)(r + PDR - hr - 1 - lo) * p32);
+            w.m = mra + (uint64_t)((uint32_t)(r - ra) * mp32);
+            auto fast = [&](auto jt, int rr) { irow_ring_fast<decltype(jt)::value>(rr, lead, rest, sb, su, sc, w); };
+            for (; r + UR + PM <= r1; r += UR) round<0, UR>(r, r1, fast);
+        }
         auto one = [&](auto jt, int rr) { irow_ring<decltype(jt)::value>(rr, r1, lead, rest, sb, su, sc); };
         unrolled_rows<UR>(r, r1, one);
     }
