@@ -201,7 +201,7 @@ static double cost_k2()
     return v;
 }
 
-static cfar_plan default_plan(const cfar_map *m)
+static cfar_plan default_plan(const cfar_map *m, bool spread)
 {
     const int hr = m->win.guard_r + m->win.train_r;
     static const int ks[3] = {2, 4, 8};
@@ -229,7 +229,7 @@ static cfar_plan default_plan(const cfar_map *m)
     // a map of few units runs on few waves, each walking its rows in turn:
     // shorter units (not below 16 rows) spread it over more of the chip
     Plan g;
-    if (plan_geometry(m, bk, out.rows_per_unit, &g) && units_of(g) < (uint64_t)min_units()) {
+    if (spread && plan_geometry(m, bk, out.rows_per_unit, &g) && units_of(g) < (uint64_t)min_units()) {
         const int64_t want = (m->rows * g.n_strips + min_units() - 1) / min_units();
         const int64_t rs = std::max<int64_t>(16, (want + 7) / 8 * 8);
         if (rs < out.rows_per_unit) out.rows_per_unit = (int)rs;
@@ -238,7 +238,9 @@ static cfar_plan default_plan(const cfar_map *m)
     return out;
 }
 
-static cfar_plan choose_plan(const cfar_map *m)
+// spread: shorten the units of a map of few units (see default_plan); a batch
+// with work enough for the chip does without.
+static cfar_plan choose_plan(const cfar_map *m, bool spread = true)
 {
     const int hr = m->win.guard_r + m->win.train_r, hf = m->win.guard_f + m->win.train_f;
     {
@@ -256,7 +258,7 @@ static cfar_plan choose_plan(const cfar_map *m)
             return out;
         }
     }
-    return default_plan(m);
+    return default_plan(m, spread);
 }
 
 static bool plan_valid(const cfar_map *m, const cfar_plan *p)
@@ -682,11 +684,21 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
 {
     std::vector<Plan> plans(n);
     uint64_t total_units = 0;
-    for (int i = 0; i < n; ++i) {
-        cfar_plan cp = forced ? *forced : choose_plan(&maps[i]);
-        if (!plan_geometry(&maps[i], cp.k_cols, cp.rows_per_unit, &plans[i], cp.ring_bytes))
-            return set_error(CFAR_EINVAL, "map %d: no valid tile plan", i);
-        total_units += units_of(plans[i]);
+    // A batch whose maps already give the chip kBatchFullUnits work units
+    // keeps every map's units at full length: shortening a small map's units
+    // (which spreads it over more waves when it runs alone) only adds warm-up
+    // rows here.  Otherwise the maps are planned as they would be alone.
+    bool spread = n == 1 || forced;
+    for (;;) {
+        total_units = 0;
+        for (int i = 0; i < n; ++i) {
+            cfar_plan cp = forced ? *forced : choose_plan(&maps[i], spread);
+            if (!plan_geometry(&maps[i], cp.k_cols, cp.rows_per_unit, &plans[i], cp.ring_bytes))
+                return set_error(CFAR_EINVAL, "map %d: no valid tile plan", i);
+            total_units += units_of(plans[i]);
+        }
+        if (spread || total_units >= (uint64_t)kBatchFullUnits) break;
+        spread = true;
     }
     if (total_units >= (uint64_t)1 << 31) return set_error(CFAR_EINVAL, "batch has too many work units");
     TiledLayout L = tiled_layout(maps, n, total_units);

@@ -37,12 +37,14 @@
 // rows still read from memory (CFAR_PDR) with it; waves per SIMD the FP32
 // kernel's registers aim at (CFAR_WAVES).  Measured on the uneven batch:
 // depth beats occupancy (2 waves per SIMD), and the ring loop gains from
-// eight rows of the far rows in flight (2.67 ms against 2.73 ms at four).
+// eight rows of the far rows in flight (2.67 ms against 2.73 ms at four),
+// but from only two rows of the lead row in flight (2.334 ms against 2.383
+// at four, 2.51 at eight and 2.49 at one).
 #ifndef CFAR_PD
 #define CFAR_PD 4
 #endif
 #ifndef CFAR_PL
-#define CFAR_PL 4
+#define CFAR_PL 2
 #endif
 #ifndef CFAR_PDR
 #define CFAR_PDR 8

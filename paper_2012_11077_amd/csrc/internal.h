@@ -177,6 +177,7 @@ constexpr int kMaxK = 8;
 constexpr int kMaxRingRows = 64;
 constexpr int kDefaultRingBytes = 12288;
 constexpr int kDefaultMinUnits = 128;
+constexpr int kBatchFullUnits = 8192;  // batched work units that fill the chip several times over
 
 inline int kset_of(int k) { return k == 8 ? 8 : 24; }
 inline int kmax_of(int kset) { return kset == 8 ? 8 : 4; }
