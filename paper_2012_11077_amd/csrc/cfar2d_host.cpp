@@ -477,12 +477,13 @@ static int min_units()
 struct KClass {
     int kset, dtype;  // kset 24: maps planned with k = 2 or 4; 8: k = 8
     bool out;         // maps of the class may write the optional outputs
+    bool wide;        // maps whose guard ring exceeds the plan's budget (a launch of their own)
     uint32_t unit_off, units, blocks;
     int ring_bytes;   // LDS ring per wave of its launch (largest need among the maps)
 };
-static int class_slot(int kset, int dtype, bool out)
+static int class_slot(int kset, int dtype, bool out, bool wide)
 {
-    return ((kset == 8 ? 1 : 0) * 2 + dtype) * 2 + (out ? 1 : 0);
+    return (((wide ? 1 : 0) * 2 + (kset == 8 ? 1 : 0)) * 2 + dtype) * 2 + (out ? 1 : 0);
 }
 static bool has_outputs(const cfar_map *m) { return m->train_sum != nullptr || m->threshold != nullptr; }
 
@@ -504,11 +505,19 @@ static int max_lds_per_block()
 
 // LDS ring bytes map m needs under its plan's budget (and what one
 // workgroup can hold besides the prefix rows).
+// The guard ring of a map, within the plan's budget; a ring the budget does
+// not hold but kRingStretchBytes does is given its own size all the same
+// (unless the plan turns the ring off with a budget of 0): the loop without
+// it loads five rows per row step, which costs more than the waves the larger
+// LDS share takes (guard 8 on a 16384^2 FP32 map: 0.98 ms without the ring,
+// 0.63 ms with an 18 KiB one).
 static int map_ring_bytes(const cfar_map *m, const Plan &p)
 {
     const int hr = m->win.guard_r + m->win.train_r;
-    const int room = max_lds_per_block() - (int)fused_lds_bytes(kset_of(p.k), 0);
-    return ring_bytes_needed(p.k, m->dtype, hr, m->win.guard_r, std::min(p.ring_bytes, std::max(room, 0)));
+    const int room = std::max(max_lds_per_block() - (int)fused_lds_bytes(kset_of(p.k), 0), 0);
+    const int need = ring_bytes_needed(p.k, m->dtype, hr, m->win.guard_r, std::min(p.ring_bytes, room));
+    if (need > 0 || p.ring_bytes <= 0) return need;
+    return ring_bytes_needed(p.k, m->dtype, hr, m->win.guard_r, std::min(std::max(p.ring_bytes, kRingStretchBytes), room));
 }
 
 // ---------------------------------------------------------------------------
@@ -660,7 +669,7 @@ static int enqueue_tiled_batch(BatchCtx *ctx, const Slot &sl, const TiledLayout 
         a.descs = descs;
         a.unit_base = (const uint32_t *)(ws + L.off_base);
         a.unit_map = (const uint32_t *)(ws + L.off_umap) + c.unit_off;
-        a.counter = &hdr->counter[class_slot(c.kset, c.dtype, c.out)];
+        a.counter = &hdr->counter[class_slot(c.kset, c.dtype, c.out, c.wide)];
         a.total_units = c.units;
         a.n_maps = n;
         a.ring_bytes = c.ring_bytes;
@@ -714,12 +723,14 @@ static int run_tiled_batch(const cfar_map *maps, int n, int flags, void *ws, siz
     for (int i = 0; i < n; ++i) {
         const int ks = kset_of(plans[i].k), dt = maps[i].dtype;
         const bool out = has_outputs(&maps[i]);
+        const bool wide = map_ring_bytes(&maps[i], plans[i]) > plans[i].ring_bytes;
         size_t c = 0;
-        while (c < classes.size() && !(classes[c].kset == ks && classes[c].dtype == dt && classes[c].out == out))
+        while (c < classes.size() && !(classes[c].kset == ks && classes[c].dtype == dt && classes[c].out == out &&
+                                       classes[c].wide == wide))
             ++c;
         if (c == classes.size()) {
             KClass kc;
-            kc.kset = ks; kc.dtype = dt; kc.out = out; kc.unit_off = 0; kc.units = 0; kc.blocks = 0;
+            kc.kset = ks; kc.dtype = dt; kc.out = out; kc.wide = wide; kc.unit_off = 0; kc.units = 0; kc.blocks = 0;
             kc.ring_bytes = 0;
             classes.push_back(kc);
             members.emplace_back();

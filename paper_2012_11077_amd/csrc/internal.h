@@ -92,7 +92,7 @@ struct PlainArgs {
 // (header + descriptors + unit tables) with one host-to-device copy; the
 // threshold tables that follow are filled on the device.
 struct BatchHeader {
-    uint32_t counter[16];  // one work counter per kernel class (k set, dtype, outputs); 8 used
+    uint32_t counter[16];  // one work counter per kernel class (wide ring, k set, dtype, outputs)
     uint32_t n_maps;
     uint32_t total_units;
     uint32_t pad[46];
@@ -176,6 +176,7 @@ constexpr int kFusedThreads = 64;  // one wave per workgroup: LDS is sized per w
 constexpr int kMaxK = 8;
 constexpr int kMaxRingRows = 64;
 constexpr int kDefaultRingBytes = 12288;
+constexpr int kRingStretchBytes = 20480;  // largest guard ring given beyond the plan's budget
 constexpr int kDefaultMinUnits = 128;
 constexpr int kBatchFullUnits = 8192;  // batched work units that fill the chip several times over
 

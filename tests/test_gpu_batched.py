@@ -136,3 +136,35 @@ def test_plain_batch_mixed_stencils():
     for k, s in enumerate(specs):
         check_full(xs_np[k], s.window, masks[k].cpu().numpy(),
                    sts[k].cpu().numpy() if outs[k] is not None else None, None, "plain")
+
+
+def test_wide_guard_rings_alone_and_in_mix():
+    """Maps whose guard ring (2 g_r + 2 rows of the strip) exceeds the default
+    LDS budget get a ring of their own size and a launch class of their own:
+    FP32 maps with guard 7 and FP64 maps with guard 3 (k = 4), mixed with
+    ordinary maps. Every map matches the oracle, alone and in the mix."""
+    wide = [synth.MapSpec(180, 700, "f32", "exp", n_targets=12, guard_r=7, guard_f=3, train_r=5, train_f=6,
+                          pfa=1e-4, seed=(41, i)) for i in range(2)]
+    wide += [synth.MapSpec(150, 640, "f64", "exp_ramp", n_targets=8, guard_r=3, guard_f=2, train_r=9, train_f=7,
+                           pfa=1e-5, seed=(42, i)) for i in range(2)]
+    for s in wide:
+        k, _, _ = C.plan_for(torch.empty((s.rows, s.cols), device=DEV,
+                                         dtype=torch.float32 if s.dtype == "f32" else torch.float64), s.window)
+        ring = (2 * s.guard_r + 2) * 64 * k * (4 if s.dtype == "f32" else 8)
+        assert k == 4 and 12288 < ring <= 20480, (s, k, ring)
+    small_specs, small_np = _small_batch(n=8, seed=11)
+    specs = wide + list(small_specs)
+    xs_np = [synth.generate(s) for s in wide] + small_np
+    xs = [torch.from_numpy(x).to(DEV) for x in xs_np]
+    wins = [s.window for s in specs]
+    masks, sts = _alloc(xs)
+    say("wide guard rings", len(wide), "in a batch of", len(xs))
+    C.cfar2d_batched(xs, wins, C.TILED, masks=masks, train_sums=sts)
+    torch.cuda.synchronize()
+    for k in range(len(xs)):
+        check_full(xs_np[k], wins[k], masks[k].cpu().numpy(), sts[k].cpu().numpy(), None, "tiled")
+    for k in range(len(wide)):
+        m = torch.empty(xs[k].shape, dtype=torch.uint8, device=DEV)
+        C.cfar2d(xs[k], wins[k], C.TILED, mask=m)
+        torch.cuda.synchronize()
+        assert np.array_equal(m.cpu().numpy(), masks[k].cpu().numpy())
