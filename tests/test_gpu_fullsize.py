@@ -96,6 +96,20 @@ def test_plain_scale_map_full_oracle():
     assert rp["mismatch"] == 0, rp
 
 
+def test_wide_guard_ring_map_full_oracle():
+    """8192 x 8192 FP32 with Table I's widest window (guard 8, background
+    12): its guard ring (18 rows of the strip) exceeds the default LDS budget
+    and takes a launch class of its own; every cell against the oracle."""
+    spec = synth.MapSpec(8192, 8192, "f32", "exp_ramp", n_targets=224, guard_r=8, guard_f=8, train_r=12,
+                         train_f=12, pfa=1e-4, seed=(71, 8192))
+    x, _, _, r = _single(spec)
+    k, _, _ = C.plan_for(x, spec.window)
+    assert k == 4 and (2 * spec.guard_r + 2) * 64 * k * 4 > 12288
+    assert r["outputs_launch_same_mask"]
+    assert r["mismatch"] == 0, r
+    assert r["max_rel_box_sum_err"] <= TILED_REL, r
+
+
 def test_uneven_batch_full_oracle():
     """All 512 maps of the uneven batch in one persistent launch, exactly as
     the benchmark runs it; every cell of every map against the oracle."""
