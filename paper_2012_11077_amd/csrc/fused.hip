@@ -455,13 +455,11 @@ struct Unit {
         ld_row<K, T>(xrow(r + gr), voff, s.b);
         ld_row<K, T>(xrow(r - hr - 1), voff, s.e);
     }
-    template <int J>
-    __device__ __forceinline__ void irow_ring(int r, int r1, T (&lead)[PL][K], RestR (&rest)[PDR], int &sb, int &su,
-                                              int &sc)
+    // The ring's part of row step r: row r+gr (b) into its slot, the cells
+    // under test (row r) and row r-gr-1 out of theirs; the slots move on.
+    __device__ __forceinline__ void ring_step(const T (&b)[K], T (&u)[K], T (&c)[K], int &sb, int &su, int &sc)
     {
-        constexpr int JL = J % PL, JR = J % PDR;
-        T u[K], c[K];
-        ring_put(sb, rest[JR].b);
+        ring_put(sb, b);
         // the reads below must see that write (the same slot when gr = 0)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -471,6 +469,14 @@ struct Unit {
         sb = sb + 1 == D ? 0 : sb + 1;
         su = su + 1 == D ? 0 : su + 1;
         sc = sc + 1 == D ? 0 : sc + 1;
+    }
+    template <int J>
+    __device__ __forceinline__ void irow_ring(int r, int r1, T (&lead)[PL][K], RestR (&rest)[PDR], int &sb, int &su,
+                                              int &sc)
+    {
+        constexpr int JL = J % PL, JR = J % PDR;
+        T u[K], c[K];
+        ring_step(rest[JR].b, u, c, sb, su, sc);
         accumulate_publish(lead[JL], rest[JR].b, c, rest[JR].e);
         load_lead(min(r + PL, r1 - 1), lead[JL]);
         load_rest(min(r + PDR, r1 - 1), rest[JR]);
@@ -494,15 +500,7 @@ struct Unit {
     {
         constexpr int JL = J % PL, JR = J % PDR;
         T u[K], c[K];
-        ring_put(sb, rest[JR].b);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        ring_get(su, u);
-        ring_get(sc, c);
-        sb = sb + 1 == D ? 0 : sb + 1;
-        su = su + 1 == D ? 0 : su + 1;
-        sc = sc + 1 == D ? 0 : sc + 1;
+        ring_step(rest[JR].b, u, c, sb, su, sc);
         accumulate_publish(lead[JL], rest[JR].b, c, rest[JR].e);
         ld_row<K, T>(rsrc(w.l, xbytes), voff, lead[JL]);
         ld_row<K, T>(rsrc(w.b, xbytes), voff, rest[JR].b);
