@@ -346,7 +346,7 @@ struct StUnit {
     int ra, rb;           // output rows of the unit
     int c_lane;           // first column of the lane (may be left of the map)
     uint32_t voff_s;      // lane byte offset into an integral-image row (kOff: left of column 0)
-    uint32_t voff_x;      // lane byte offset into a map row
+    uint32_t voff_x;      // lane byte offset into a map row (kOff: a lane without outputs)
     uint32_t moff, poff;  // mask byte offsets: full ownership / partial (kOff: none)
     bool part;            // some lane owns only part of its K columns (wave-uniform)
     bool edge;            // the strip holds the map's last column (wave-uniform)
@@ -385,8 +385,10 @@ struct StUnit {
         const int c0 = c_out0 - d.st_halo;
         c_lane = c0 + lane * K;
         voff_s = c_lane >= 0 ? (uint32_t)c_lane * 8u : kOff;
-        voff_x = c_lane >= 0 ? (uint32_t)c_lane * (uint32_t)sizeof(T) : kOff;
         const bool own = c_lane >= c_out0 && c_lane < c_out1;
+        // the map is read only for the cells under test: lanes without
+        // outputs (the halo) read nothing
+        voff_x = own ? (uint32_t)c_lane * (uint32_t)sizeof(T) : kOff;
         const bool full = own && c_lane + K <= c_out1;
         moff = full ? (uint32_t)c_lane : kOff;
         poff = own && !full ? (uint32_t)c_lane : kOff;
