@@ -141,17 +141,21 @@ def test_plain_batch_mixed_stencils():
 def test_wide_guard_rings_alone_and_in_mix():
     """Maps whose guard ring (2 g_r + 2 rows of the strip) exceeds the default
     LDS budget get a ring of their own size and a launch class of their own:
-    FP32 maps with guard 7 and FP64 maps with guard 3 (k = 4), mixed with
-    ordinary maps. Every map matches the oracle, alone and in the mix."""
+    FP32 maps with guard 7 and FP64 maps with guard 3 (k = 4), an FP32 map
+    with guard 4 and a window wide enough for k = 8, mixed with ordinary
+    maps. Every map matches the oracle, alone and in the mix."""
     wide = [synth.MapSpec(180, 700, "f32", "exp", n_targets=12, guard_r=7, guard_f=3, train_r=5, train_f=6,
                           pfa=1e-4, seed=(41, i)) for i in range(2)]
     wide += [synth.MapSpec(150, 640, "f64", "exp_ramp", n_targets=8, guard_r=3, guard_f=2, train_r=9, train_f=7,
                            pfa=1e-5, seed=(42, i)) for i in range(2)]
+    # a window too wide for k = 4 (k = 8, 512-column strips) with guard 4
+    wide += [synth.MapSpec(200, 700, "f32", "exp", n_targets=6, guard_r=4, guard_f=4, train_r=6, train_f=128,
+                           pfa=1e-4, seed=(43, 0))]
     for s in wide:
         k, _, _ = C.plan_for(torch.empty((s.rows, s.cols), device=DEV,
                                          dtype=torch.float32 if s.dtype == "f32" else torch.float64), s.window)
         ring = (2 * s.guard_r + 2) * 64 * k * (4 if s.dtype == "f32" else 8)
-        assert k == 4 and 12288 < ring <= 20480, (s, k, ring)
+        assert k == (8 if s.train_f > 60 else 4) and 12288 < ring <= 20480, (s, k, ring)
     small_specs, small_np = _small_batch(n=8, seed=11)
     specs = wide + list(small_specs)
     xs_np = [synth.generate(s) for s in wide] + small_np
