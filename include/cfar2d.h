@@ -211,8 +211,10 @@ typedef struct {
     int32_t rows_per_unit; /* output rows per work unit, 1..4096                                  */
     int32_t ring_bytes;    /* LDS bytes per wave for the guard ring, 0..65536, or -1 for the
                             * library default (12 KiB): the rows r-g_r-1 .. r+g_r of the strip,
-                            * when they fit, so a row step loads three rows instead of five;
-                            * 0 = no ring.  Results do not depend on it. */
+                            * when they fit, so a row step loads three rows instead of five.  A
+                            * ring that needs more than a positive budget but at most 20 KiB is
+                            * given its own size (batched: in a launch of its own); 0 = no ring.
+                            * Results do not depend on it. */
 } cfar_plan;
 
 /* The plan the TILED form uses for map m (from the loaded table, else the
